@@ -1,0 +1,230 @@
+"""Benchmark of the batched Fossen RK4 step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-plain]
+
+Workload (one "step" = one episode of the hot path over one batch):
+  1,048,576 envs, half BlueROV2 (6 thrusters) and half BlueROV2 Heavy
+  (8 thrusters), FP32, +-20 % uniform parameter randomisation, quadratic
+  throttle map with a 0.05 s thruster lag; each step resets every env
+  (parameters + per-env factorisation of M = M_RB + M_A), then runs 200
+  control steps, each one fused launch per class of 16 RK4 sub-steps of 5 ms
+  with the episode statistics, replayed from a HIP graph.  Actions (6.7 GB),
+  initial states and multipliers are generated once, seeded, and are resident
+  in HBM before timing starts.
+
+Prints one JSON line.  `value` is env-steps/s where an env-step is one RK4
+sub-step of one environment (one Fossen RK4 step).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "env-steps/s of batched Fossen RK4 step at 1M envs; served p50/p99 latency"
+PEAK_FP32_VALU = 157.3e12      # MI355X published FP32 vector peak (packed)
+PEAK_FP32_UNPACKED = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_HBM = 8.0e12
+
+
+def rhs_flops(n_thr, lag):
+    """Flops of one right-hand side as the kernel formulates it (FMA = 2)."""
+    return 160 + 12 * n_thr + (2 * n_thr if lag else 0)
+
+
+def substep_flops(n_thr, lag):
+    """Four right-hand sides, the RK4 combination (13 flops per state component) and
+    the quaternion renormalisation (12)."""
+    D = 13 + (n_thr if lag else 0)
+    return 4 * rhs_flops(n_thr, lag) + 13 * D + 12
+
+
+def plain_bytes(n_thr, lag):
+    """Algorithmic HBM bytes of one env-substep in the plain kernel: state read+write,
+    the throttle frame, the 23 randomised parameters."""
+    D = 13 + (n_thr if lag else 0)
+    return 4 * (2 * D + n_thr + 23)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2410_14117_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key):
+    """HBM traffic per launch from the committed rocprofv3 --pmc summary, if it was taken
+    on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get(kernel_key)
+
+
+def cpu_baseline(n_envs=8192, n_ctrl=200):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    from oracle import oracle
+    from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
+                           actions, param_multipliers, env_classes)
+    c = CONFIGS["c3"]
+    classes = [vehicle_variant(BLUEROV2, thr_map=1, thr_tau=0.05),
+               vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)]
+    cls = env_classes(n_envs, "halves")
+    x0 = initial_state(n_envs, 21, c.seed_base + 2)
+    act = actions(n_ctrl, 8, n_envs, c.seed_base + 3)
+    mult = param_multipliers(n_envs, c.rho, c.seed_base + 1)
+    oracle.build()
+    threads = oracle.lib().or_max_threads()
+    t0 = time.perf_counter()
+    oracle.rollout(classes, x0, act, c.substeps, c.dt_sub, env_class=cls, mult=mult,
+                   want_stats=True, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n_envs * n_ctrl * c.substeps / dt, "unit": "env-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n_envs} envs (half BlueROV2, half Heavy) x {n_ctrl} control steps x "
+                      f"{c.substeps} RK4 sub-steps, FP64, with statistics; {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-envs", type=int, default=1 << 20)
+    ap.add_argument("--n-ctrl", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the environments are independent and this "
+              "build runs no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_14117_amd import mg
+    from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
+                           action_frames, param_multipliers, env_classes)
+
+    c = CONFIGS["c3"]
+    E, T, S = args.n_envs, args.n_ctrl, c.substeps
+    classes = [vehicle_variant(BLUEROV2, thr_map=1, thr_tau=0.05),
+               vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)]
+    cls = env_classes(E, "halves")
+    n_b = int((cls == 0).sum())
+    n_h = E - n_b
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # inputs, resident in HBM before timing
+    x0 = torch.from_numpy(initial_state(E, 21, c.seed_base + 2)).to(dev)
+    mult = torch.from_numpy(param_multipliers(E, c.rho, c.seed_base + 1)).to(dev)
+    act = torch.empty((T, 8, E), dtype=torch.float32, device=dev)
+    for t, fr in enumerate(action_frames(T, 8, E, c.seed_base + 3)):
+        act[t].copy_(torch.from_numpy(fr))
+    stats = torch.empty((T, 4), dtype=torch.float64, device=dev)
+
+    sim = mg.Sim(classes, E, c.dt_sub, S, env_class=cls)
+
+    def step(plain=False):
+        sim.reset(state=x0, param_mult=mult)
+        sim.rollout(act, stats=stats, plain=plain)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    env_substeps = E * T * S
+    value = env_substeps * args.steps / wall
+
+    # dominant kernel: the fused step, timed alone (graph replays only) with HIP events
+    sim.reset(state=x0, param_mult=mult)
+    sim.rollout(act, stats=stats)            # graph already cached
+    torch.cuda.synchronize()
+    reps = max(2, args.steps)
+    ev0.record(stream)
+    for _ in range(reps):
+        sim.rollout(act, stats=stats)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    fused_ms = ev0.elapsed_time(ev1) / reps
+    launches = 2 * T
+    flops_rollout = (n_b * substep_flops(6, True) + n_h * substep_flops(8, True)) * T * S
+    achieved = flops_rollout / (fused_ms * 1e-3)
+    st = stats.cpu().numpy()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "env-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c3: 1,048,576 envs (half BlueROV2 / half BlueROV2 Heavy), "
+                               "+-20% randomisation, quadratic thrust + 0.05 s lag, "
+                               "200 control steps x 16 RK4 sub-steps of 5 ms per step, "
+                               "fused launch per control step from a HIP graph",
+                   "n_envs": E, "control_steps": T, "substeps_per_launch": S, "dt_sub": c.dt_sub},
+        "env_control_steps_per_s": E * T * args.steps / wall,
+        "sim_seconds_per_wall_second": value * c.dt_sub,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": load_traffic("k_step_fused"),
+                     "kernel": "k_step<6|8,lag> fused, 16 sub-steps per launch",
+                     "avg_launch_us": fused_ms * 1e3 / launches,
+                     "flops_per_env_substep": {"bluerov2": substep_flops(6, True),
+                                               "heavy": substep_flops(8, True)},
+                     "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED},
+        "stats_last_step": {"mean_dist": st[-1, 0] / max(1, E - st[-1, 3]),
+                            "max_dist": st[-1, 1], "nonfinite": st[-1, 3]},
+    }
+
+    if not args.no_plain:
+        sim.reset(state=x0, param_mult=mult)
+        sim.rollout(act, stats=stats, plain=True)     # capture
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(2):
+            sim.rollout(act, stats=stats, plain=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = ev0.elapsed_time(ev1) / 2
+        bytes_rollout = (n_b * plain_bytes(6, True) + n_h * plain_bytes(8, True)) * T * S
+        out["plain"] = {
+            "env_steps_per_s": env_substeps / (plain_ms * 1e-3),
+            "ms_per_rollout": plain_ms, "launches": 2 * T * S,
+            "avg_launch_us": plain_ms * 1e3 / (2 * T * S),
+            "achieved_GBps_algorithmic": bytes_rollout / (plain_ms * 1e-3) / 1e9,
+            "frac_hbm": bytes_rollout / (plain_ms * 1e-3) / PEAK_HBM,
+            "speedup_fused_vs_plain": plain_ms / fused_ms,
+        }
+    sim.close()
+    del act
+    torch.cuda.empty_cache()
+
+    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * mg.h -- C ABI of the MI355X batched Fossen 6-DOF simulator (libmg.so).
+ *
+ * The library steps many independent underwater-vehicle environments through
+ * Fossen's equation of motion as MarineGym states it (Sec. II "Method",
+ * Eq. (1)): rigid-body plus added mass, rigid-body plus added-mass Coriolis,
+ * linear plus quadratic damping, weight and buoyancy, driven by per-thruster
+ * throttles (Eq. (3)) through a thruster allocation matrix, with several
+ * sub-steps per control step (Sec. II, the paragraph after Eq. (1)), many
+ * parallel environment instances and per-env domain randomisation (Sec. II,
+ * first paragraph; Sec. III).  Integration is classical RK4 in FP32 with the
+ * attitude quaternion renormalised after every sub-step.
+ *
+ * Conventions common to every call
+ *   Units      SI.  World frame north-east-down, body frame forward-right-down,
+ *              origin (CO) at the centre of buoyancy.
+ *   State      one column per env, component-major (SoA) FP32:
+ *                [x y z | qw qx qy qz | u v w p q r | f_1 .. f_n]
+ *              p = NED position, q = Hamilton scalar-first unit quaternion
+ *              body->NED, nu = body velocities, f = thruster states (present
+ *              only for classes with a thruster lag).  The I/O width D =
+ *              mg_state_dim() = 13 + the largest thruster count among lagged
+ *              classes; rows a class does not use read as 0.
+ *   Layout     every array argument is row-major [rows][n_envs] (or
+ *              [frames][rows][n_envs]) in the caller's env order, FP32 unless
+ *              stated; "device" pointers are HIP device memory of the sim's
+ *              device, "host" pointers are ordinary host memory.
+ *   Ownership  the sim owns every buffer it allocates; the caller owns every
+ *              pointer it passes and keeps it alive until the work queued on
+ *              the sim's stream has completed.
+ *   Ordering   calls are enqueued on the sim's stream and return at once
+ *              (except where "synchronous" is stated).
+ *   Errors     every call returns an mg_status.  Argument errors return
+ *              MG_ERR_INVALID with no side effect.  A failed HIP call makes
+ *              the sim sticky: it and every later call return MG_ERR_DEVICE.
+ *              An env whose state becomes non-finite is not an error: it is
+ *              counted in the episode statistics and keeps propagating NaN.
+ *              mg_last_error() gives a text for the last failure.
+ *   Threads    a sim is thread-compatible (one thread at a time); distinct
+ *              sims may be used from distinct threads.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MG_ABI_VERSION 1u
+#define MG_MAX_THRUSTERS 8
+#define MG_MAX_CLASSES 16
+#define MG_NUM_PARAMS 23  /* m, Ixx, Iyy, Izz, M_A(6), D_L(6), D_Q(6), B */
+#define MG_NUM_THETA 19   /* differentiable subset: M_A(6), D_L(6), D_Q(6), B */
+#define MG_NUM_STATS 4    /* sum dist, max dist, sum kinetic energy, non-finite count */
+
+typedef int32_t mg_status;
+#define MG_OK 0
+#define MG_ERR_INVALID 1     /* bad argument; nothing was done */
+#define MG_ERR_OOM 2         /* device allocation failed */
+#define MG_ERR_DEVICE 3      /* a HIP call failed; the sim is unusable */
+#define MG_ERR_UNSUPPORTED 4 /* valid description this GPU path does not implement */
+#define MG_ERR_BUSY 5        /* server queue full / request not finished */
+
+typedef struct mg_sim mg_sim;
+
+/* One vehicle class (Sec. II: BlueROV2 / BlueROV2 Heavy), raw preset numbers.
+ *   mass, inertia  rigid-body mass (kg) and principal inertia about the CG (kg m^2)
+ *   r_g, r_b       CG and CB w.r.t. the CO (m); the GPU path requires the x
+ *                  and y components to be 0 (MG_ERR_UNSUPPORTED otherwise)
+ *   added_mass     diagonal of M_A; d_lin, d_quad: diagonal linear and
+ *                  quadratic damping; buoyancy B (N).  Weight W = 9.81 m.
+ *   thr_pos/dir    position (m) and unit direction of positive thrust of each
+ *                  of the n_thr (1..8) thrusters; column i of the allocation
+ *                  matrix is [dir_i ; pos_i x dir_i]
+ *   f_max          thrust at throttle 1 (N); thr_map 0: f = f_max a,
+ *                  1: f = f_max a|a|, with a clamped to [-1, 1]
+ *   thr_tau        first-order thruster lag (s); 0 = thrust follows the
+ *                  command instantly (no thruster state) */
+typedef struct {
+  double mass, inertia[3], r_g[3], r_b[3], added_mass[6], d_lin[6], d_quad[6], buoyancy;
+  double thr_pos[MG_MAX_THRUSTERS][3], thr_dir[MG_MAX_THRUSTERS][3], f_max, thr_tau;
+  int32_t n_thr, thr_map;
+} mg_vehicle;
+
+/* Simulator description.
+ *   abi_version  must be MG_ABI_VERSION
+ *   n_envs       number of environments E (>= 1)
+ *   classes      host array of n_classes (1..MG_MAX_CLASSES) vehicles
+ *   env_class    host [n_envs] class index per env, or NULL (all class 0);
+ *                envs are regrouped internally so that every wavefront holds
+ *                one class; the ABI always speaks the caller's env order
+ *   dt_sub       RK4 sub-step (s) and substeps = sub-steps per control step
+ *   device       HIP device ordinal; stream: hipStream_t or NULL (default) */
+typedef struct {
+  uint32_t abi_version;
+  int32_t n_classes;
+  int64_t n_envs;
+  const mg_vehicle* classes;
+  const int32_t* env_class;
+  double dt_sub;
+  int32_t substeps;
+  int32_t device;
+  void* stream;
+} mg_config;
+
+uint32_t mg_abi_version(void);
+const char* mg_status_str(mg_status s);
+/* Text of the last failure of this sim, or of the last failed mg_create when
+ * sim is NULL.  Valid until the next call on the same sim. */
+const char* mg_last_error(const mg_sim* sim);
+
+/* Allocates the device buffers (state, parameters, derived constants) and
+ * leaves every env at rest at the origin with nominal parameters (as
+ * mg_reset with NULL state and multipliers).  Synchronous. */
+mg_status mg_create(const mg_config* cfg, mg_sim** out);
+/* Waits for the sim's stream and frees everything; NULL is ignored. */
+void mg_destroy(mg_sim* sim);
+mg_status mg_set_stream(mg_sim* sim, void* stream);
+int32_t mg_state_dim(const mg_sim* sim);      /* D, or -1 for NULL */
+int32_t mg_action_dim(const mg_sim* sim);     /* N_max = largest n_thr, or -1 */
+int64_t mg_num_envs(const mg_sim* sim);       /* E, or -1 */
+
+/* Domain randomisation and reset (Sec. II: physical-parameter randomisation).
+ *   env_ids     device int64 [n_ids] caller env indices, or NULL for all envs
+ *               (then n_ids must be 0 or E); out-of-range ids are skipped
+ *   state       device [D][n_ids] new states, or NULL: at rest at the origin,
+ *               identity attitude, zero thruster state
+ *   param_mult  device [23][n_ids] multipliers of the class's nominal
+ *               parameters, or NULL (nominal).  Here the per-env mass matrix
+ *               M = M_RB + M_A and its inverse are formed once (in FP64,
+ *               rounded to FP32) and kept for every later step; an env whose
+ *               M is not positive definite gets NaN constants and shows up as
+ *               non-finite after its next step. */
+mg_status mg_reset(mg_sim* sim, const int64_t* env_ids, int64_t n_ids, const float* state,
+                   const float* param_mult);
+/* Absolute parameters for all envs, device [23][E] (same order as the
+ * multipliers), refactoring M as mg_reset does.  State is untouched. */
+mg_status mg_set_params(mg_sim* sim, const float* params);
+/* Overwrites every env's state from device [D][E]; parameters are kept. */
+mg_status mg_set_state(mg_sim* sim, const float* state);
+
+/* Advances every env by n_ctrl control steps in ONE fused launch per class:
+ * each control step reads one throttle frame, holds it for `substeps` RK4
+ * sub-steps, and the state stays in registers across all n_ctrl * substeps
+ * sub-steps (Sec. II: several sub-simulation steps per simulation step).
+ *   actions  device [n_ctrl][N_max][E] throttles (rows >= a class's n_thr are ignored)
+ *   targets  device [3][E] station-keeping targets for the statistics, or NULL (origin)
+ *   traj     device [n_ctrl][D][E] state after each control step, or NULL
+ *   stats    device double [n_ctrl][4] per control step, over envs with a
+ *            finite state: sum and max of |p - target| (the Task-1 error of
+ *            Eq. (4)), sum of kinetic energy 1/2 nu^T M nu; and the number of
+ *            envs whose state is not finite.  Deterministic (fixed-order
+ *            two-pass reduction).  Or NULL. */
+mg_status mg_step(mg_sim* sim, const float* actions, int32_t n_ctrl, const float* targets,
+                  float* traj, double* stats);
+/* Same result as mg_step, computed by the plain kernel: one launch per RK4
+ * sub-step per class, state round-tripping HBM between launches. */
+mg_status mg_step_plain(mg_sim* sim, const float* actions, int32_t n_ctrl, const float* targets,
+                        float* traj, double* stats);
+/* T control steps as T launches per class (plain != 0: T * substeps
+ * launches), replayed from a HIP graph that is captured on first use and
+ * cached for this exact argument tuple.  Arguments as mg_step with n_ctrl = T. */
+mg_status mg_rollout(mg_sim* sim, const float* actions, int32_t T, const float* targets,
+                     float* traj, double* stats, int32_t plain);
+/* Copies the state [D][E] to out.  out_on_device != 0: device pointer,
+ * enqueued; 0: host pointer, synchronous (waits for the stream). */
+mg_status mg_get_state(mg_sim* sim, float* out, int32_t out_on_device);
+/* Copies the absolute parameters [23][E], same rules as mg_get_state. */
+mg_status mg_get_params(mg_sim* sim, float* out, int32_t out_on_device);
+/* Waits for the sim's stream; returns MG_ERR_DEVICE if queued work failed. */
+mg_status mg_synchronize(mg_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MG_H */

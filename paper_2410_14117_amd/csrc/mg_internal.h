@@ -1,0 +1,96 @@
+// mg_internal.h -- structures shared by the host runtime and the kernel
+// translation units of libmg (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mg {
+
+constexpr int kMaxThr = 8;
+constexpr int kNumParams = 23;
+constexpr int kNumDerived = 30;
+constexpr int kNumTheta = 19;
+constexpr int kBlock = 256;      // threads per block of the step kernels (4 wave64)
+constexpr int kSegAlign = 64;    // each class segment starts on a wavefront boundary
+constexpr double kG0 = 9.81;
+
+// Rows of the per-env derived-constant table [kNumDerived][Ep], formed once at
+// reset.  With I_g and M_A diagonal and r_g = (0,0,z_g) the mass matrix only
+// couples (u,q) and (v,p), so M and M^-1 have 8 distinct entries each.
+enum DerivedRow : int {
+  kMuu = 0, kMvv, kMww, kMpp, kMqq, kMrr, kMuq, kMvp,     // M
+  kIuu = 8, kIvv, kIww, kIpp, kIqq, kIrr, kIuq, kIvp,     // M^-1
+  kDL = 16,                                               // 6 rows
+  kDQ = 22,                                               // 6 rows
+  kWmB = 28,                                              // W - B
+  kHz = 29,                                               // W z_g - B z_b
+};
+
+// Wave-uniform constants of one vehicle class, passed by value (kernarg ->
+// scalar registers).
+struct ClassConst {
+  float B[6][kMaxThr];   // allocation matrix
+  float f_max;
+  float inv_tau;         // 1 / thruster lag (0 if none)
+  int32_t n_thr;
+  int32_t thr_map;       // 0 linear, 1 quadratic
+  int32_t lag;
+  int32_t pad_;
+};
+
+// Nominal parameters of a class for the reset kernel (device table).
+struct ClassNominal {
+  double p[kNumParams];
+  double zg, zb;
+  int32_t n_thr, lag;
+};
+
+struct StepArgs {
+  float* state;                // internal [D][Ep]
+  const float* derived;        // internal [kNumDerived][Ep]
+  int64_t Ep;                  // internal row stride
+  int64_t E;                   // caller row stride
+  const int32_t* perm;         // internal -> caller index, NULL = identity
+  int64_t seg_start, seg_len;  // this class's internal range
+  const float* actions;        // caller [n_ctrl][n_max][E]
+  int32_t n_max;
+  const float* targets;        // caller [3][E] or NULL
+  float* traj;                 // caller [n_ctrl][D][E] or NULL
+  int32_t D;                   // I/O state width
+  double* partials;            // [n_ctrl][nblk_total][4] or NULL
+  int32_t nblk_total, blk_off;
+  int32_t n_ctrl, substeps;
+  float dt;
+};
+
+struct ResetArgs {
+  float* state;                // internal [D][Ep]
+  float* params;               // internal [23][Ep] absolute
+  float* derived;              // internal [kNumDerived][Ep]
+  int64_t Ep, E;
+  int32_t D;
+  const int32_t* iperm;        // caller -> internal, NULL = identity
+  const uint8_t* class_of;     // internal [Ep] class of each env
+  const ClassNominal* nominal; // device [n_classes]
+  const int64_t* ids;          // caller ids [n] or NULL (= 0..n-1)
+  int64_t n;
+  const float* state_in;       // [D][n] or NULL (rest)
+  const float* param_in;       // [23][n] or NULL (nominal)
+  int32_t param_absolute;      // param_in holds absolute values (else multipliers)
+  int32_t write_state;         // 0: keep the state
+};
+
+// launchers (kernels_step.hip)
+hipError_t launch_step(const ClassConst& cc, const StepArgs& a, hipStream_t s);
+hipError_t launch_stats_finalize(const double* partials, int32_t nblk, int32_t n_ctrl,
+                                 double* stats, hipStream_t s);
+hipError_t launch_reset(const ResetArgs& a, hipStream_t s);
+// out[r][perm[j]] = in[r][j] for rows r < rows (internal -> caller order)
+hipError_t launch_gather_out(const float* in, int64_t Ep, float* out, int64_t E, int32_t rows,
+                             const int32_t* perm, int64_t n_internal, hipStream_t s);
+// out[r][j] = in[r][perm[j]] (caller -> internal order), padding lanes untouched
+hipError_t launch_scatter_in(const float* in, int64_t E, float* out, int64_t Ep, int32_t rows,
+                             const int32_t* perm, int64_t n_internal, hipStream_t s);
+
+}  // namespace mg

@@ -1,0 +1,578 @@
+// runtime.hip -- host side of libmg: the sim context (SoA device buffers,
+// class-grouped env layout, per-class constants), argument checking, launch
+// sequencing, HIP-graph cache and the exported C ABI of include/mg.h.
+#include "mg.h"
+#include "mg_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace mg;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct GraphKey {
+  int32_t T, plain;
+  const void *actions, *targets, *traj, *stats;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(T, plain, actions, targets, traj, stats) <
+           std::tie(o.T, o.plain, o.actions, o.targets, o.traj, o.stats);
+  }
+};
+
+}  // namespace
+
+struct mg_sim {
+  int device = 0;
+  hipStream_t stream = nullptr;      // caller's stream (not owned)
+  hipStream_t cap_stream = nullptr;  // owned, used only to capture graphs
+  bool broken = false;
+  std::string err;
+
+  int64_t E = 0, Ep = 0;
+  int32_t D = 13, n_max = 1, substeps = 1, n_classes = 1;
+  double dt = 0.01;
+  int32_t nblk_total = 0;
+
+  std::vector<ClassConst> cc;
+  std::vector<ClassNominal> nominal;
+  std::vector<int64_t> seg_start, seg_len;
+  std::vector<int32_t> seg_blk_off;
+
+  float* state = nullptr;      // [D][Ep]
+  float* params = nullptr;     // [23][Ep]
+  float* derived = nullptr;    // [kNumDerived][Ep]
+  int32_t* perm = nullptr;     // [Ep] internal -> caller (-1 for padding), NULL = identity
+  int32_t* iperm = nullptr;    // [E] caller -> internal, NULL = identity
+  uint8_t* class_of = nullptr; // [Ep]
+  ClassNominal* nominal_dev = nullptr;
+  double* partials = nullptr;
+  size_t partials_cap = 0;     // doubles
+  float* staging = nullptr;    // [max(D,23)][E] for host copies with a permuted layout
+  std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+mg_status fail(mg_sim* s, mg_status code, const std::string& msg) {
+  if (s) {
+    s->err = msg;
+    if (code == MG_ERR_DEVICE) s->broken = true;
+  } else {
+    g_create_error = msg;
+  }
+  return code;
+}
+
+#define MG_HIP(sim, call)                                                               \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail((sim), MG_ERR_DEVICE,                                                 \
+                  std::string(#call) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+// Makes the sim's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+mg_status check_usable(mg_sim* s) {
+  if (!s) return MG_ERR_INVALID;
+  if (s->broken) return MG_ERR_DEVICE;
+  return MG_OK;
+}
+
+void clear_graphs(mg_sim* s) {
+  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+}
+
+// Class constants the step kernels read from scalar registers.  The
+// allocation matrix is formed here from the thruster geometry: column i is
+// [d_i ; r_i x d_i].
+ClassConst make_class_const(const mg_vehicle& v) {
+  ClassConst c;
+  std::memset(&c, 0, sizeof(c));
+  for (int i = 0; i < v.n_thr; ++i) {
+    const double* r = v.thr_pos[i];
+    const double* d = v.thr_dir[i];
+    const double col[6] = {d[0], d[1], d[2], r[1] * d[2] - r[2] * d[1],
+                           r[2] * d[0] - r[0] * d[2], r[0] * d[1] - r[1] * d[0]};
+    for (int k = 0; k < 6; ++k) c.B[k][i] = (float)col[k];
+  }
+  c.f_max = (float)v.f_max;
+  c.inv_tau = v.thr_tau > 0.0 ? (float)(1.0 / v.thr_tau) : 0.0f;
+  c.n_thr = v.n_thr;
+  c.thr_map = v.thr_map;
+  c.lag = v.thr_tau > 0.0 ? 1 : 0;
+  return c;
+}
+
+ClassNominal make_nominal(const mg_vehicle& v) {
+  ClassNominal n;
+  std::memset(&n, 0, sizeof(n));
+  n.p[0] = v.mass;
+  for (int i = 0; i < 3; ++i) n.p[1 + i] = v.inertia[i];
+  for (int i = 0; i < 6; ++i) {
+    n.p[4 + i] = v.added_mass[i];
+    n.p[10 + i] = v.d_lin[i];
+    n.p[16 + i] = v.d_quad[i];
+  }
+  n.p[22] = v.buoyancy;
+  n.zg = v.r_g[2];
+  n.zb = v.r_b[2];
+  n.n_thr = v.n_thr;
+  n.lag = v.thr_tau > 0.0 ? 1 : 0;
+  return n;
+}
+
+bool finite_all(const double* p, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+mg_status validate_vehicle(const mg_vehicle& v, int idx, std::string& why, bool& unsupported) {
+  unsupported = false;
+  char buf[160];
+  if (v.n_thr < 1 || v.n_thr > MG_MAX_THRUSTERS) {
+    std::snprintf(buf, sizeof buf, "class %d: n_thr %d outside 1..%d", idx, v.n_thr,
+                  MG_MAX_THRUSTERS);
+    why = buf;
+    return MG_ERR_INVALID;
+  }
+  if (v.thr_map != 0 && v.thr_map != 1) {
+    std::snprintf(buf, sizeof buf, "class %d: thr_map must be 0 or 1", idx);
+    why = buf;
+    return MG_ERR_INVALID;
+  }
+  const double scal[4] = {v.mass, v.buoyancy, v.f_max, v.thr_tau};
+  if (!finite_all(scal, 4) || !finite_all(v.inertia, 3) || !finite_all(v.added_mass, 6) ||
+      !finite_all(v.d_lin, 6) || !finite_all(v.d_quad, 6) || !finite_all(v.r_g, 3) ||
+      !finite_all(v.r_b, 3) || !finite_all(&v.thr_pos[0][0], 3 * v.n_thr) ||
+      !finite_all(&v.thr_dir[0][0], 3 * v.n_thr) || v.thr_tau < 0.0) {
+    std::snprintf(buf, sizeof buf, "class %d: non-finite or negative lag parameter", idx);
+    why = buf;
+    return MG_ERR_INVALID;
+  }
+  if (v.r_g[0] != 0.0 || v.r_g[1] != 0.0 || v.r_b[0] != 0.0 || v.r_b[1] != 0.0) {
+    std::snprintf(buf, sizeof buf,
+                  "class %d: the GPU path needs r_g and r_b on the body z axis", idx);
+    why = buf;
+    unsupported = true;
+    return MG_ERR_UNSUPPORTED;
+  }
+  return MG_OK;
+}
+
+mg_status ensure_partials(mg_sim* s, int32_t n_ctrl) {
+  const size_t need = (size_t)std::max(n_ctrl, 1) * (size_t)s->nblk_total * 4;
+  if (need <= s->partials_cap) return MG_OK;
+  // a graph may hold the old buffer: drop the cache before freeing it
+  MG_HIP(s, hipStreamSynchronize(s->stream));
+  clear_graphs(s);
+  if (s->partials) MG_HIP(s, hipFree(s->partials));
+  s->partials = nullptr;
+  s->partials_cap = 0;
+  if (hipMalloc(&s->partials, need * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    s->partials = nullptr;
+    return fail(s, MG_ERR_OOM, "partials allocation failed");
+  }
+  s->partials_cap = need;
+  return MG_OK;
+}
+
+// Enqueue n_ctrl fused control steps (plain = 0) or their plain equivalent
+// (one launch per sub-step), followed by the statistics pass.
+mg_status enqueue_steps(mg_sim* s, hipStream_t st, const float* actions, int32_t n_ctrl,
+                        const float* targets, float* traj, double* stats, bool plain,
+                        bool one_launch_per_ctrl) {
+  StepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.state = s->state;
+  a.derived = s->derived;
+  a.Ep = s->Ep;
+  a.E = s->E;
+  a.perm = s->perm;
+  a.n_max = s->n_max;
+  a.targets = targets;
+  a.D = s->D;
+  a.nblk_total = s->nblk_total;
+  a.dt = (float)s->dt;
+  const int64_t frame = (int64_t)s->n_max * s->E;
+  const int64_t tframe = (int64_t)s->D * s->E;
+  const int64_t pframe = (int64_t)s->nblk_total * 4;
+  if (!plain && !one_launch_per_ctrl) {
+    a.actions = actions;
+    a.traj = traj;
+    a.partials = stats ? s->partials : nullptr;
+    a.n_ctrl = n_ctrl;
+    a.substeps = s->substeps;
+    for (int k = 0; k < s->n_classes; ++k) {
+      a.seg_start = s->seg_start[k];
+      a.seg_len = s->seg_len[k];
+      a.blk_off = s->seg_blk_off[k];
+      MG_HIP(s, launch_step(s->cc[k], a, st));
+    }
+  } else {
+    const int32_t n_sub = plain ? s->substeps : 1;
+    for (int32_t t = 0; t < n_ctrl; ++t) {
+      for (int32_t sub = 0; sub < n_sub; ++sub) {
+        const bool last = sub == n_sub - 1;
+        a.actions = actions + t * frame;
+        a.traj = (traj && last) ? traj + t * tframe : nullptr;
+        a.partials = (stats && last) ? s->partials + t * pframe : nullptr;
+        a.n_ctrl = 1;
+        a.substeps = plain ? 1 : s->substeps;
+        for (int k = 0; k < s->n_classes; ++k) {
+          a.seg_start = s->seg_start[k];
+          a.seg_len = s->seg_len[k];
+          a.blk_off = s->seg_blk_off[k];
+          MG_HIP(s, launch_step(s->cc[k], a, st));
+        }
+      }
+    }
+  }
+  if (stats) MG_HIP(s, launch_stats_finalize(s->partials, s->nblk_total, n_ctrl, stats, st));
+  return MG_OK;
+}
+
+mg_status reset_impl(mg_sim* s, const int64_t* ids, int64_t n, const float* state_in,
+                     const float* param_in, int absolute, int write_state) {
+  ResetArgs r;
+  std::memset(&r, 0, sizeof(r));
+  r.state = s->state;
+  r.params = s->params;
+  r.derived = s->derived;
+  r.Ep = s->Ep;
+  r.E = s->E;
+  r.D = s->D;
+  r.iperm = s->iperm;
+  r.class_of = s->class_of;
+  r.nominal = s->nominal_dev;
+  r.ids = ids;
+  r.n = n;
+  r.state_in = state_in;
+  r.param_in = param_in;
+  r.param_absolute = absolute;
+  r.write_state = write_state;
+  MG_HIP(s, launch_reset(r, s->stream));
+  return MG_OK;
+}
+
+// internal [rows][Ep] -> caller [rows][E] at out (device), or via staging to host
+mg_status copy_out(mg_sim* s, const float* src, int32_t rows, float* out, int32_t on_device) {
+  if (!out) return fail(s, MG_ERR_INVALID, "output pointer is NULL");
+  float* dst = on_device ? out : s->staging;
+  if (!s->perm) {
+    MG_HIP(s, hipMemcpy2DAsync(dst, s->E * sizeof(float), src, s->Ep * sizeof(float),
+                               s->E * sizeof(float), rows, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    MG_HIP(s, launch_gather_out(src, s->Ep, dst, s->E, rows, s->perm, s->Ep, s->stream));
+  }
+  if (!on_device) {
+    MG_HIP(s, hipMemcpyAsync(out, s->staging, (size_t)rows * s->E * sizeof(float),
+                             hipMemcpyDeviceToHost, s->stream));
+    MG_HIP(s, hipStreamSynchronize(s->stream));
+  }
+  return MG_OK;
+}
+
+mg_status step_common(mg_sim* s, const float* actions, int32_t n_ctrl, const float* targets,
+                      float* traj, double* stats, bool plain) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!actions) return fail(s, MG_ERR_INVALID, "actions is NULL");
+  if (n_ctrl < 1) return fail(s, MG_ERR_INVALID, "n_ctrl must be >= 1");
+  DeviceGuard g(s->device);
+  if (stats && (st = ensure_partials(s, n_ctrl))) return st;
+  return enqueue_steps(s, s->stream, actions, n_ctrl, targets, traj, stats, plain, false);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t mg_abi_version(void) { return MG_ABI_VERSION; }
+
+const char* mg_status_str(mg_status s) {
+  switch (s) {
+    case MG_OK: return "ok";
+    case MG_ERR_INVALID: return "invalid argument";
+    case MG_ERR_OOM: return "out of device memory";
+    case MG_ERR_DEVICE: return "device error";
+    case MG_ERR_UNSUPPORTED: return "unsupported";
+    case MG_ERR_BUSY: return "busy";
+    default: return "unknown status";
+  }
+}
+
+const char* mg_last_error(const mg_sim* sim) {
+  return sim ? sim->err.c_str() : g_create_error.c_str();
+}
+
+mg_status mg_create(const mg_config* cfg, mg_sim** out) {
+  if (!out) return fail(nullptr, MG_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(nullptr, MG_ERR_INVALID, "cfg is NULL");
+  if (cfg->abi_version != MG_ABI_VERSION) return fail(nullptr, MG_ERR_INVALID, "ABI version mismatch");
+  if (cfg->n_envs < 1 || cfg->n_envs > ((int64_t)1 << 31) - 1024)
+    return fail(nullptr, MG_ERR_INVALID, "n_envs outside 1 .. 2^31 - 1024");
+  if (cfg->n_classes < 1 || cfg->n_classes > MG_MAX_CLASSES || !cfg->classes)
+    return fail(nullptr, MG_ERR_INVALID, "n_classes outside 1..16 or classes NULL");
+  if (!(cfg->dt_sub > 0.0) || !std::isfinite(cfg->dt_sub) || cfg->substeps < 1)
+    return fail(nullptr, MG_ERR_INVALID, "dt_sub must be > 0 and substeps >= 1");
+  for (int k = 0; k < cfg->n_classes; ++k) {
+    std::string why;
+    bool unsup;
+    mg_status st = validate_vehicle(cfg->classes[k], k, why, unsup);
+    if (st) return fail(nullptr, st, why);
+  }
+  const int64_t E = cfg->n_envs;
+  std::vector<int64_t> count(cfg->n_classes, 0);
+  if (cfg->env_class) {
+    for (int64_t e = 0; e < E; ++e) {
+      const int32_t c = cfg->env_class[e];
+      if (c < 0 || c >= cfg->n_classes) return fail(nullptr, MG_ERR_INVALID, "env_class out of range");
+      ++count[c];
+    }
+  } else {
+    count[0] = E;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(nullptr, MG_ERR_DEVICE, "no HIP device");
+  }
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(nullptr, MG_ERR_INVALID, "bad device ordinal");
+
+  mg_sim* s = new mg_sim();
+  s->device = cfg->device;
+  s->stream = (hipStream_t)cfg->stream;
+  s->E = E;
+  s->n_classes = cfg->n_classes;
+  s->substeps = cfg->substeps;
+  s->dt = cfg->dt_sub;
+  int32_t dmax = 13, nmax = 1;
+  for (int k = 0; k < cfg->n_classes; ++k) {
+    const mg_vehicle& v = cfg->classes[k];
+    s->cc.push_back(make_class_const(v));
+    s->nominal.push_back(make_nominal(v));
+    nmax = std::max(nmax, v.n_thr);
+    if (v.thr_tau > 0.0) dmax = std::max(dmax, 13 + v.n_thr);
+  }
+  s->D = dmax;
+  s->n_max = nmax;
+  // class segments, each starting on a wavefront boundary
+  int64_t off = 0;
+  int32_t blk = 0;
+  for (int k = 0; k < cfg->n_classes; ++k) {
+    s->seg_start.push_back(off);
+    s->seg_len.push_back(count[k]);
+    s->seg_blk_off.push_back(blk);
+    blk += (int32_t)((count[k] + kBlock - 1) / kBlock);
+    off += (count[k] + kSegAlign - 1) / kSegAlign * kSegAlign;
+  }
+  s->Ep = std::max<int64_t>(off, kSegAlign);
+  s->nblk_total = blk;
+  std::vector<int32_t> perm(s->Ep, -1), iperm(E);
+  std::vector<uint8_t> cls(s->Ep, 0);
+  {
+    std::vector<int64_t> fill(s->seg_start);
+    for (int64_t e = 0; e < E; ++e) {
+      const int32_t c = cfg->env_class ? cfg->env_class[e] : 0;
+      const int64_t j = fill[c]++;
+      perm[j] = (int32_t)e;
+      iperm[e] = (int32_t)j;
+    }
+    for (int k = 0; k < cfg->n_classes; ++k)
+      for (int64_t j = s->seg_start[k]; j < s->seg_start[k] + ((count[k] + kSegAlign - 1) / kSegAlign) * kSegAlign; ++j)
+        cls[j] = (uint8_t)k;
+  }
+  bool identity = true;
+  for (int64_t e = 0; e < E && identity; ++e) identity = iperm[e] == e;
+
+  DeviceGuard g(s->device);
+  auto bail = [&](mg_status code, const std::string& msg) {
+    g_create_error = msg;
+    mg_destroy(s);
+    return code;
+  };
+  const size_t Ep = (size_t)s->Ep;
+  if (hipMalloc(&s->state, Ep * s->D * sizeof(float)) != hipSuccess ||
+      hipMalloc(&s->params, Ep * kNumParams * sizeof(float)) != hipSuccess ||
+      hipMalloc(&s->derived, Ep * kNumDerived * sizeof(float)) != hipSuccess ||
+      hipMalloc(&s->class_of, Ep) != hipSuccess ||
+      hipMalloc(&s->nominal_dev, sizeof(ClassNominal) * s->n_classes) != hipSuccess ||
+      hipMalloc(&s->staging, (size_t)E * std::max(s->D, kNumParams) * sizeof(float)) != hipSuccess ||
+      (!identity && (hipMalloc(&s->perm, Ep * sizeof(int32_t)) != hipSuccess ||
+                     hipMalloc(&s->iperm, (size_t)E * sizeof(int32_t)) != hipSuccess))) {
+    (void)hipGetLastError();
+    return bail(MG_ERR_OOM, "device allocation failed in mg_create");
+  }
+  if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipMemset(s->state, 0, Ep * s->D * sizeof(float)) != hipSuccess ||
+      hipMemset(s->params, 0, Ep * kNumParams * sizeof(float)) != hipSuccess ||
+      hipMemset(s->derived, 0, Ep * kNumDerived * sizeof(float)) != hipSuccess ||
+      hipMemcpy(s->class_of, cls.data(), Ep, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(s->nominal_dev, s->nominal.data(), sizeof(ClassNominal) * s->n_classes,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      (!identity && (hipMemcpy(s->perm, perm.data(), Ep * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+                     hipMemcpy(s->iperm, iperm.data(), (size_t)E * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess))) {
+    (void)hipGetLastError();
+    return bail(MG_ERR_DEVICE, "device initialisation failed in mg_create");
+  }
+  if (reset_impl(s, nullptr, E, nullptr, nullptr, 0, 1) != MG_OK ||
+      hipStreamSynchronize(s->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(MG_ERR_DEVICE, "initial reset failed: " + s->err);
+  }
+  *out = s;
+  return MG_OK;
+}
+
+void mg_destroy(mg_sim* s) {
+  if (!s) return;
+  {
+    DeviceGuard g(s->device);
+    if (s->stream || s->state) (void)hipStreamSynchronize(s->stream);
+    clear_graphs(s);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    void* bufs[] = {s->state, s->params, s->derived, s->perm, s->iperm, s->class_of,
+                    s->nominal_dev, s->partials, s->staging};
+    for (void* b : bufs)
+      if (b) (void)hipFree(b);
+    (void)hipGetLastError();
+  }
+  delete s;
+}
+
+mg_status mg_set_stream(mg_sim* s, void* stream) {
+  if (!s) return MG_ERR_INVALID;
+  s->stream = (hipStream_t)stream;
+  return MG_OK;
+}
+
+int32_t mg_state_dim(const mg_sim* s) { return s ? s->D : -1; }
+int32_t mg_action_dim(const mg_sim* s) { return s ? s->n_max : -1; }
+int64_t mg_num_envs(const mg_sim* s) { return s ? s->E : -1; }
+
+mg_status mg_reset(mg_sim* s, const int64_t* env_ids, int64_t n_ids, const float* state,
+                   const float* param_mult) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  int64_t n = n_ids;
+  if (!env_ids) {
+    if (n_ids != 0 && n_ids != s->E) return fail(s, MG_ERR_INVALID, "n_ids must be 0 or n_envs when env_ids is NULL");
+    n = s->E;
+  } else if (n_ids < 0) {
+    return fail(s, MG_ERR_INVALID, "n_ids < 0");
+  }
+  DeviceGuard g(s->device);
+  return reset_impl(s, env_ids, n, state, param_mult, 0, 1);
+}
+
+mg_status mg_set_params(mg_sim* s, const float* params) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!params) return fail(s, MG_ERR_INVALID, "params is NULL");
+  DeviceGuard g(s->device);
+  return reset_impl(s, nullptr, s->E, nullptr, params, 1, 0);
+}
+
+mg_status mg_set_state(mg_sim* s, const float* state) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!state) return fail(s, MG_ERR_INVALID, "state is NULL");
+  DeviceGuard g(s->device);
+  if (!s->perm) {
+    MG_HIP(s, hipMemcpy2DAsync(s->state, s->Ep * sizeof(float), state, s->E * sizeof(float),
+                               s->E * sizeof(float), s->D, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    MG_HIP(s, launch_scatter_in(state, s->E, s->state, s->Ep, s->D, s->perm, s->Ep, s->stream));
+  }
+  return MG_OK;
+}
+
+mg_status mg_step(mg_sim* s, const float* actions, int32_t n_ctrl, const float* targets,
+                  float* traj, double* stats) {
+  return step_common(s, actions, n_ctrl, targets, traj, stats, false);
+}
+
+mg_status mg_step_plain(mg_sim* s, const float* actions, int32_t n_ctrl, const float* targets,
+                        float* traj, double* stats) {
+  return step_common(s, actions, n_ctrl, targets, traj, stats, true);
+}
+
+mg_status mg_rollout(mg_sim* s, const float* actions, int32_t T, const float* targets,
+                     float* traj, double* stats, int32_t plain) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!actions) return fail(s, MG_ERR_INVALID, "actions is NULL");
+  if (T < 1) return fail(s, MG_ERR_INVALID, "T must be >= 1");
+  DeviceGuard g(s->device);
+  if (stats && (st = ensure_partials(s, T))) return st;
+  GraphKey key{T, plain ? 1 : 0, actions, targets, traj, stats};
+  auto it = s->graphs.find(key);
+  if (it == s->graphs.end()) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    MG_HIP(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    mg_status est = enqueue_steps(s, s->cap_stream, actions, T, targets, traj, stats, plain != 0, true);
+    hipError_t ce = hipStreamEndCapture(s->cap_stream, &graph);
+    if (est) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return est;
+    }
+    if (ce != hipSuccess) return fail(s, MG_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(s, MG_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    it = s->graphs.emplace(key, exec).first;
+  }
+  MG_HIP(s, hipGraphLaunch(it->second, s->stream));
+  return MG_OK;
+}
+
+mg_status mg_get_state(mg_sim* s, float* out, int32_t out_on_device) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  DeviceGuard g(s->device);
+  return copy_out(s, s->state, s->D, out, out_on_device);
+}
+
+mg_status mg_get_params(mg_sim* s, float* out, int32_t out_on_device) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  DeviceGuard g(s->device);
+  return copy_out(s, s->params, kNumParams, out, out_on_device);
+}
+
+mg_status mg_synchronize(mg_sim* s) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  DeviceGuard g(s->device);
+  MG_HIP(s, hipStreamSynchronize(s->stream));
+  MG_HIP(s, hipGetLastError());
+  return MG_OK;
+}
+
+}  // extern "C"

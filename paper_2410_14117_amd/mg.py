@@ -1,0 +1,266 @@
+"""Python binding of libmg (include/mg.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libmg.so; torch tensors serve as
+device memory and torch's current HIP stream as the stream.  If the library
+is missing the binding raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmg.so")
+
+MG_ABI_VERSION = 1
+MAX_THR = 8
+NUM_PARAMS = 23
+NUM_THETA = 19
+NUM_STATS = 4
+
+MG_OK, MG_ERR_INVALID, MG_ERR_OOM, MG_ERR_DEVICE, MG_ERR_UNSUPPORTED, MG_ERR_BUSY = range(6)
+
+
+class MgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mg status {status}: {msg}")
+        self.status = status
+
+
+class MgVehicle(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("inertia", ctypes.c_double * 3),
+        ("r_g", ctypes.c_double * 3), ("r_b", ctypes.c_double * 3),
+        ("added_mass", ctypes.c_double * 6), ("d_lin", ctypes.c_double * 6),
+        ("d_quad", ctypes.c_double * 6), ("buoyancy", ctypes.c_double),
+        ("thr_pos", (ctypes.c_double * 3) * MAX_THR), ("thr_dir", (ctypes.c_double * 3) * MAX_THR),
+        ("f_max", ctypes.c_double), ("thr_tau", ctypes.c_double),
+        ("n_thr", ctypes.c_int32), ("thr_map", ctypes.c_int32),
+    ]
+
+
+class MgConfig(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32), ("n_classes", ctypes.c_int32),
+        ("n_envs", ctypes.c_int64), ("classes", ctypes.POINTER(MgVehicle)),
+        ("env_class", ctypes.POINTER(ctypes.c_int32)), ("dt_sub", ctypes.c_double),
+        ("substeps", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+    ]
+
+
+_vp = ctypes.c_void_p
+_SIGS = {
+    "mg_abi_version": (ctypes.c_uint32, []),
+    "mg_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+    "mg_last_error": (ctypes.c_char_p, [_vp]),
+    "mg_create": (ctypes.c_int32, [ctypes.POINTER(MgConfig), ctypes.POINTER(_vp)]),
+    "mg_destroy": (None, [_vp]),
+    "mg_set_stream": (ctypes.c_int32, [_vp, _vp]),
+    "mg_state_dim": (ctypes.c_int32, [_vp]),
+    "mg_action_dim": (ctypes.c_int32, [_vp]),
+    "mg_num_envs": (ctypes.c_int64, [_vp]),
+    "mg_reset": (ctypes.c_int32, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
+    "mg_set_params": (ctypes.c_int32, [_vp, _vp]),
+    "mg_set_state": (ctypes.c_int32, [_vp, _vp]),
+    "mg_step": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "mg_step_plain": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "mg_rollout": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32]),
+    "mg_get_state": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
+    "mg_get_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
+    "mg_synchronize": (ctypes.c_int32, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmg.so (built by ``python -m paper_2410_14117_amd.build``); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2410_14117_amd.build` (there is no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        if L.mg_abi_version() != MG_ABI_VERSION:
+            raise ImportError("libmg ABI version mismatch")
+        _lib = L
+    return _lib
+
+
+def vehicle_struct(preset):
+    v = MgVehicle()
+    v.mass = preset["mass"]
+    for i in range(3):
+        v.inertia[i] = preset["inertia"][i]
+        v.r_g[i] = preset["r_g"][i]
+        v.r_b[i] = preset["r_b"][i]
+    for i in range(6):
+        v.added_mass[i] = preset["added_mass"][i]
+        v.d_lin[i] = preset["d_lin"][i]
+        v.d_quad[i] = preset["d_quad"][i]
+    v.buoyancy = preset["buoyancy"]
+    n = len(preset["thr_pos"])
+    if not 1 <= n <= MAX_THR or len(preset["thr_dir"]) != n:
+        raise ValueError("a vehicle needs 1..8 thrusters with a position and a direction each")
+    for i in range(n):
+        for k in range(3):
+            v.thr_pos[i][k] = preset["thr_pos"][i][k]
+            v.thr_dir[i][k] = preset["thr_dir"][i][k]
+    v.n_thr = n
+    v.f_max = preset["f_max"]
+    v.thr_map = int(preset["thr_map"])
+    v.thr_tau = float(preset["thr_tau"])
+    return v
+
+
+def _ptr(t, dtype, shape, name):
+    """Device pointer of a contiguous CUDA tensor with the given dtype/shape (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _current_stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Sim:
+    """A batch of environments on one GPU (wraps an ``mg_sim``)."""
+
+    def __init__(self, classes, n_envs, dt_sub, substeps, env_class=None, device=0):
+        L = lib()
+        if isinstance(classes, dict):
+            classes = [classes]
+        self._classes = (MgVehicle * len(classes))(*[vehicle_struct(c) for c in classes])
+        cfg = MgConfig()
+        cfg.abi_version = MG_ABI_VERSION
+        cfg.n_classes = len(classes)
+        cfg.n_envs = int(n_envs)
+        cfg.classes = self._classes
+        ec = None
+        if env_class is not None:
+            ec = np.ascontiguousarray(np.asarray(env_class, dtype=np.int32))
+            if ec.shape != (n_envs,):
+                raise ValueError("env_class must have shape [n_envs]")
+            cfg.env_class = ec.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        cfg.dt_sub = float(dt_sub)
+        cfg.substeps = int(substeps)
+        cfg.device = int(device)
+        cfg.stream = _current_stream()
+        h = _vp()
+        st = L.mg_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != MG_OK:
+            raise MgError(st, L.mg_last_error(None).decode())
+        self._h = h
+        self.device = int(device)
+        self.n_envs = int(n_envs)
+        self.state_dim = L.mg_state_dim(h)
+        self.action_dim = L.mg_action_dim(h)
+        self.dt_sub = float(dt_sub)
+        self.substeps = int(substeps)
+
+    # -- plumbing --------------------------------------------------------------------------
+    def _check(self, st):
+        if st != MG_OK:
+            raise MgError(st, lib().mg_last_error(self._h).decode())
+
+    def _bind_stream(self):
+        self._check(lib().mg_set_stream(self._h, _current_stream()))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls -----------------------------------------------------------------------------
+    def reset(self, env_ids=None, state=None, param_mult=None):
+        import torch
+        n = self.n_envs if env_ids is None else int(env_ids.numel())
+        ids = _ptr(env_ids, torch.int64, (n,), "env_ids")
+        s = _ptr(state, torch.float32, (self.state_dim, n), "state")
+        m = _ptr(param_mult, torch.float32, (NUM_PARAMS, n), "param_mult")
+        self._bind_stream()
+        self._check(lib().mg_reset(self._h, ids, n if env_ids is not None else 0, s, m))
+
+    def set_params(self, params):
+        import torch
+        p = _ptr(params, torch.float32, (NUM_PARAMS, self.n_envs), "params")
+        self._bind_stream()
+        self._check(lib().mg_set_params(self._h, p))
+
+    def set_state(self, state):
+        import torch
+        s = _ptr(state, torch.float32, (self.state_dim, self.n_envs), "state")
+        self._bind_stream()
+        self._check(lib().mg_set_state(self._h, s))
+
+    def _step_args(self, actions, n_ctrl, targets, traj, stats):
+        import torch
+        E, D, N = self.n_envs, self.state_dim, self.action_dim
+        a = _ptr(actions, torch.float32, (n_ctrl, N, E), "actions")
+        tg = _ptr(targets, torch.float32, (3, E), "targets")
+        tr = _ptr(traj, torch.float32, (n_ctrl, D, E), "traj")
+        stt = _ptr(stats, torch.float64, (n_ctrl, NUM_STATS), "stats")
+        return a, tg, tr, stt
+
+    def step(self, actions, targets=None, traj=None, stats=None, plain=False):
+        """actions [n_ctrl][N_max][E]: n_ctrl control steps fused in one launch per class."""
+        n_ctrl = int(actions.shape[0])
+        a, tg, tr, st = self._step_args(actions, n_ctrl, targets, traj, stats)
+        self._bind_stream()
+        fn = lib().mg_step_plain if plain else lib().mg_step
+        self._check(fn(self._h, a, n_ctrl, tg, tr, st))
+
+    def rollout(self, actions, targets=None, traj=None, stats=None, plain=False):
+        """actions [T][N_max][E]: T launches per class replayed from a cached HIP graph."""
+        T = int(actions.shape[0])
+        a, tg, tr, st = self._step_args(actions, T, targets, traj, stats)
+        self._bind_stream()
+        self._check(lib().mg_rollout(self._h, a, T, tg, tr, st, 1 if plain else 0))
+
+    def get_state(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.state_dim, self.n_envs), dtype=torch.float32,
+                              device=f"cuda:{self.device}")
+        p = _ptr(out, torch.float32, (self.state_dim, self.n_envs), "out")
+        self._bind_stream()
+        self._check(lib().mg_get_state(self._h, p, 1))
+        return out
+
+    def get_params(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((NUM_PARAMS, self.n_envs), dtype=torch.float32,
+                              device=f"cuda:{self.device}")
+        p = _ptr(out, torch.float32, (NUM_PARAMS, self.n_envs), "out")
+        self._bind_stream()
+        self._check(lib().mg_get_params(self._h, p, 1))
+        return out
+
+    def synchronize(self):
+        self._check(lib().mg_synchronize(self._h))

@@ -1,0 +1,92 @@
+"""C-ABI contract tests that need no GPU: the library loads, exports every
+function include/mg.h declares, and rejects bad arguments without side effects."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_14117_amd import mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mg.lib()
+    names = _declared("mg.h")
+    assert "mg_create" in names and "mg_step" in names and "mg_rollout" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_abi_version_and_status_strings():
+    L = mg.lib()
+    assert L.mg_abi_version() == mg.MG_ABI_VERSION
+    for s in range(6):
+        assert L.mg_status_str(s)
+    assert L.mg_status_str(99) == b"unknown status"
+
+
+def _cfg(preset, n_envs=64, **kw):
+    v = (mg.MgVehicle * 1)(mg.vehicle_struct(preset))
+    c = mg.MgConfig()
+    c.abi_version = kw.get("abi_version", mg.MG_ABI_VERSION)
+    c.n_classes = kw.get("n_classes", 1)
+    c.n_envs = n_envs
+    c.classes = v
+    c.dt_sub = kw.get("dt_sub", 0.01)
+    c.substeps = kw.get("substeps", 1)
+    c.device = kw.get("device", 0)
+    c.stream = None
+    return c, v
+
+
+def test_create_rejects_bad_arguments():
+    from workloads import BLUEROV2, vehicle_variant
+    L = mg.lib()
+    h = ctypes.c_void_p()
+    assert L.mg_create(None, ctypes.byref(h)) == mg.MG_ERR_INVALID
+    assert L.mg_create(ctypes.byref(_cfg(BLUEROV2)[0]), None) == mg.MG_ERR_INVALID
+    for kw in [dict(abi_version=99), dict(n_classes=0), dict(dt_sub=0.0), dict(dt_sub=float("nan")),
+               dict(substeps=0)]:
+        c, _keep = _cfg(BLUEROV2, **kw)
+        assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_INVALID
+        assert h.value is None
+    c, _keep = _cfg(BLUEROV2, n_envs=0)
+    assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_INVALID
+    bad = vehicle_variant(BLUEROV2, thr_map=3)
+    c, _keep = _cfg(bad)
+    assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_INVALID
+    assert b"thr_map" in L.mg_last_error(None)
+    off_axis = vehicle_variant(BLUEROV2, r_g=[0.01, 0.0, 0.02])
+    c, _keep = _cfg(off_axis)
+    assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_UNSUPPORTED
+
+
+def test_null_sim_calls_are_safe():
+    L = mg.lib()
+    L.mg_destroy(None)
+    assert L.mg_state_dim(None) == -1
+    assert L.mg_num_envs(None) == -1
+    assert L.mg_step(None, None, 1, None, None, None) == mg.MG_ERR_INVALID
+    assert L.mg_reset(None, None, 0, None, None) == mg.MG_ERR_INVALID
+    assert L.mg_synchronize(None) == mg.MG_ERR_INVALID
+
+
+def test_create_without_device_reports_device_error():
+    """On a host with no GPU mg_create fails with MG_ERR_DEVICE (never a CPU fallback)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from workloads import BLUEROV2
+    L = mg.lib()
+    h = ctypes.c_void_p()
+    c, _keep = _cfg(BLUEROV2)
+    assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_DEVICE
+    assert h.value is None

@@ -1,0 +1,321 @@
+"""GPU parity of the HIP step path (through the C ABI) against the FP64 oracle.
+
+Tolerances: one control step <= 1e-5 and whole trajectories <= 1e-3 in the
+norm max |x_gpu - x_ref| / max(1, |x_ref|), from identical FP32 inputs.
+"""
+import numpy as np
+import pytest
+
+from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
+                       random_states, actions, action_frames, param_multipliers, env_classes)
+from tests.gpu_util import dev, host, rel_err, say, TOL_ONE_STEP, TOL_TRAJ
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mgmod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_14117_amd import mg
+    mg.lib()
+    return mg
+
+
+LAGGED = {
+    "bluerov2": vehicle_variant(BLUEROV2, thr_map=1, thr_tau=0.05),
+    "heavy": vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05),
+}
+
+
+def _run(mgmod, classes, x0, act, dt, S, env_class=None, mult=None, targets=None, mode="fused"):
+    E = x0.shape[1]
+    sim = mgmod.Sim(classes, E, dt, S, env_class=env_class)
+    sim.reset(state=dev(x0), param_mult=None if mult is None else dev(mult))
+    T = act.shape[0]
+    traj = torch.empty((T, sim.state_dim, E), dtype=torch.float32, device="cuda")
+    stats = torch.empty((T, 4), dtype=torch.float64, device="cuda")
+    a = dev(act)
+    tg = None if targets is None else dev(targets)
+    if mode == "fused":
+        sim.step(a, targets=tg, traj=traj, stats=stats)
+    elif mode == "plain":
+        sim.step(a, targets=tg, traj=traj, stats=stats, plain=True)
+    else:
+        sim.rollout(a, targets=tg, traj=traj, stats=stats, plain=(mode == "graph_plain"))
+    torch.cuda.synchronize()
+    out = host(traj), host(stats), host(sim.get_state())
+    sim.close()
+    return out
+
+
+def test_c1_full_trajectory(mgmod, oracle):
+    c = CONFIGS["c1"]
+    say("c1 64 envs x 1000 steps, fused single launch")
+    x0 = initial_state(c.n_envs, 13, c.seed_base + 2)
+    act = actions(c.n_ctrl, 6, c.n_envs, c.seed_base + 3)
+    traj, stats, xT = _run(mgmod, BLUEROV2, x0, act, c.dt_sub, c.substeps)
+    ref = oracle.rollout(BLUEROV2, x0, act, c.substeps, c.dt_sub, want_traj=True, want_stats=True)
+    assert rel_err(traj[0], ref["traj"][0]) <= TOL_ONE_STEP
+    assert rel_err(traj, ref["traj"]) <= TOL_TRAJ
+    np.testing.assert_array_equal(xT, traj[-1])
+    assert np.all(stats[:, 3] == 0)
+    np.testing.assert_allclose(stats[:, :3], ref["stats"][:, :3], rtol=1e-4)
+
+
+@pytest.mark.parametrize("variant", ["c1_linear", "c2_heavy_lag", "mixed_lag"])
+def test_one_control_step_over_the_envelope(mgmod, oracle, variant):
+    """One control step from states spread over the operating envelope (random attitude,
+    up to 1.5 m/s and 2 rad/s, saturated thrusters), ragged env count, randomised params."""
+    E = 4096 + 37
+    if variant == "c1_linear":
+        classes, cls, dt, S, D, N = [BLUEROV2], None, 0.01, 1, 13, 6
+    elif variant == "c2_heavy_lag":
+        classes, cls, dt, S, D, N = [LAGGED["heavy"]], None, 0.005, 4, 21, 8
+    else:
+        classes, dt, S, D, N = [LAGGED["bluerov2"], LAGGED["heavy"]], 0.005, 4, 21, 8
+        cls = env_classes(E, "bernoulli", 99)
+    say("one step", variant, E)
+    x0 = random_states(E, D, 31)
+    if cls is not None:
+        x0[19:, cls == 0] = 0.0
+    act = actions(1, N, E, 32) * np.float32(1.3)      # some throttles saturate
+    mult = param_multipliers(E, 0.2, 33)
+    traj, stats, _ = _run(mgmod, classes, x0, act, dt, S, env_class=cls, mult=mult)
+    ref = oracle.rollout(classes, x0, act, S, dt, env_class=cls, mult=mult, want_traj=True,
+                         want_stats=True)
+    assert rel_err(traj[0], ref["traj"][0]) <= TOL_ONE_STEP
+    np.testing.assert_allclose(stats[0, :3], ref["stats"][0, :3], rtol=1e-5)
+    assert stats[0, 3] == ref["stats"][0, 3] == 0
+
+
+def test_c2_trajectory_on_env_subset(mgmod, oracle):
+    c = CONFIGS["c2"]
+    v = LAGGED["heavy"]
+    say("c2 4096 heavy x 1000 control x 4 substeps, graph rollout")
+    x0 = initial_state(c.n_envs, 21, c.seed_base + 2)
+    act = actions(c.n_ctrl, 8, c.n_envs, c.seed_base + 3)
+    mult = param_multipliers(c.n_envs, c.rho, c.seed_base + 1)
+    traj, stats, xT = _run(mgmod, v, x0, act, c.dt_sub, c.substeps, mult=mult, mode="graph")
+    sub = np.arange(0, c.n_envs, 8)
+    ref = oracle.rollout(v, x0[:, sub], act[:, :, sub], c.substeps, c.dt_sub, mult=mult[:, sub],
+                         want_traj=True)
+    assert rel_err(traj[0][:, sub], ref["traj"][0]) <= TOL_ONE_STEP
+    assert rel_err(traj[:, :, sub], ref["traj"]) <= TOL_TRAJ
+    # full-env statistics against the oracle's, over all 4096 envs for the last step only
+    full = oracle.rollout(v, x0, act[:2], c.substeps, c.dt_sub, mult=mult, want_stats=True)
+    _, st2, _ = _run(mgmod, v, x0, act[:2], c.dt_sub, c.substeps, mult=mult)
+    np.testing.assert_allclose(st2[:, :3], full["stats"][:, :3], rtol=1e-5)
+
+
+def test_fused_plain_graph_agree(mgmod):
+    """One fused launch of n_ctrl x S sub-steps, per-control-step graph launches and the plain
+    per-sub-step kernel give the same states (bitwise) and statistics."""
+    E, T = 3000, 40
+    classes = [LAGGED["bluerov2"], LAGGED["heavy"]]
+    cls = env_classes(E, "halves")
+    x0 = initial_state(E, 21, 41)
+    x0[19:, cls == 0] = 0
+    act = actions(T, 8, E, 42)
+    mult = param_multipliers(E, 0.2, 43)
+    tgt = np.random.default_rng(44).normal(size=(3, E)).astype(np.float32)
+    res = {}
+    for mode in ["fused", "plain", "graph", "graph_plain"]:
+        say("mode", mode)
+        res[mode] = _run(mgmod, classes, x0, act, 0.005, 4, env_class=cls, mult=mult,
+                         targets=tgt, mode=mode)
+    for mode in ["plain", "graph", "graph_plain"]:
+        np.testing.assert_array_equal(res[mode][0], res["fused"][0])
+        np.testing.assert_array_equal(res[mode][1], res["fused"][1])
+
+
+def test_interleaved_classes_match_contiguous(mgmod, oracle):
+    """Envs of two classes in arbitrary order are regrouped internally; results come back in
+    the caller's order and equal a contiguous layout bitwise."""
+    E, T = 1000, 25
+    classes = [LAGGED["bluerov2"], LAGGED["heavy"]]
+    cls = env_classes(E, "bernoulli", 51)
+    order = np.argsort(cls, kind="stable")
+    x0 = initial_state(E, 21, 52)
+    x0[19:, cls == 0] = 0
+    act = actions(T, 8, E, 53)
+    mult = param_multipliers(E, 0.2, 54)
+    say("interleaved classes", E)
+    tr_i, st_i, _ = _run(mgmod, classes, x0, act, 0.005, 4, env_class=cls, mult=mult)
+    tr_c, st_c, _ = _run(mgmod, classes, x0[:, order], act[:, :, order], 0.005, 4,
+                         env_class=cls[order], mult=mult[:, order])
+    np.testing.assert_array_equal(tr_i[:, :, order], tr_c)
+    np.testing.assert_allclose(st_i, st_c, rtol=1e-12)
+    ref = oracle.rollout(classes, x0, act, 4, 0.005, env_class=cls, mult=mult, want_traj=True)
+    assert rel_err(tr_i, ref["traj"]) <= 1e-4
+
+
+@pytest.mark.parametrize("E", [1, 63, 65, 257, 1000])
+def test_ragged_sizes(mgmod, oracle, E):
+    say("ragged", E)
+    v = LAGGED["heavy"]
+    x0 = initial_state(E, 21, 61)
+    act = actions(50, 8, E, 62)
+    mult = param_multipliers(E, 0.2, 63)
+    tr, st, _ = _run(mgmod, v, x0, act, 0.005, 4, mult=mult)
+    ref = oracle.rollout(v, x0, act, 4, 0.005, mult=mult, want_traj=True, want_stats=True)
+    assert rel_err(tr[0], ref["traj"][0]) <= TOL_ONE_STEP
+    assert rel_err(tr, ref["traj"]) <= 1e-4
+    np.testing.assert_allclose(st[:, :3], ref["stats"][:, :3], rtol=1e-5)
+
+
+def test_reset_subset_params_and_resume(mgmod):
+    E = 300
+    v = LAGGED["heavy"]
+    sim = mgmod.Sim(v, E, 0.005, 4)
+    mult = param_multipliers(E, 0.2, 71)
+    x0 = initial_state(E, 21, 72)
+    sim.reset(state=dev(x0), param_mult=dev(mult))
+    # absolute parameters are nominal x multiplier, rounded once to FP32
+    nominal = np.array([v["mass"], *v["inertia"], *v["added_mass"], *v["d_lin"], *v["d_quad"],
+                        v["buoyancy"]])
+    expect = (nominal[:, None] * mult.astype(np.float64)).astype(np.float32)
+    np.testing.assert_array_equal(host(sim.get_params()), expect)
+    np.testing.assert_array_equal(host(sim.get_state()), x0)
+    # partial reset of three envs
+    ids = torch.tensor([5, 17, 299], dtype=torch.int64, device="cuda")
+    xs = random_states(3, 21, 73)
+    sim.reset(env_ids=ids, state=dev(xs), param_mult=dev(np.ones((23, 3), np.float32)))
+    got = host(sim.get_state())
+    expect_x = x0.copy()
+    expect_x[:, [5, 17, 299]] = xs
+    np.testing.assert_array_equal(got, expect_x)
+    p = host(sim.get_params())
+    np.testing.assert_array_equal(p[:, 17], nominal.astype(np.float32))
+    np.testing.assert_array_equal(p[:, 16], expect[:, 16])
+    # checkpoint / resume is bitwise
+    act = dev(actions(20, 8, E, 74))
+    sim.step(act[:10])
+    snap_x = sim.get_state().clone()
+    snap_p = sim.get_params().clone()
+    sim.step(act[10:])
+    ref = host(sim.get_state())
+    sim2 = mgmod.Sim(v, E, 0.005, 4)
+    sim2.set_params(snap_p)
+    sim2.set_state(snap_x)
+    sim2.step(act[10:])
+    np.testing.assert_array_equal(host(sim2.get_state()), ref)
+    sim.close()
+    sim2.close()
+
+
+def test_nonfinite_env_is_counted_and_isolated(mgmod):
+    E, T = 512, 12
+    v = LAGGED["heavy"]
+    x0 = initial_state(E, 21, 81)
+    act = actions(T, 8, E, 82)
+    bad = act.copy()
+    bad[3, 1, 100] = np.nan
+    mult = param_multipliers(E, 0.2, 83)
+    mult[0, 200] = -2.0                  # mass -23 kg: M not positive definite
+    say("non-finite")
+    tr_ok, st_ok, _ = _run(mgmod, v, x0, act, 0.005, 4, mult=mult)
+    tr_bad, st_bad, _ = _run(mgmod, v, x0, bad, 0.005, 4, mult=mult)
+    assert np.all(np.isnan(tr_ok[:, :, 200]).any(axis=1))
+    assert np.all(st_ok[:, 3] == 1)
+    assert list(st_bad[:, 3]) == [1, 1, 1] + [2] * (T - 3)
+    keep = np.setdiff1d(np.arange(E), [100])
+    np.testing.assert_array_equal(tr_bad[:, :, keep], tr_ok[:, :, keep])
+
+
+def test_heave_steady_state_on_gpu(mgmod):
+    """Closed form: d_l w + d_q w|w| = F for a pure heave thrust (no oracle involved)."""
+    import math
+    E, T = 64, 3000
+    x0 = np.zeros((13, E), np.float32)
+    x0[3] = 1
+    act = np.zeros((T, 6, E), np.float32)
+    act[:, 4:] = 0.5
+    tr, _, _ = _run(mgmod, BLUEROV2, x0, act, 0.01, 1)
+    F = -40.0
+    w = -(-5.0 + math.sqrt(25 + 4 * 37 * 40.0)) / (2 * 37)
+    np.testing.assert_allclose(tr[-1, 9], w, rtol=2e-6)
+    assert np.abs(tr[-1, [7, 8, 10, 11, 12]]).max() < 1e-6
+    assert np.abs(F) > 0
+
+
+def test_run_to_run_determinism(mgmod):
+    E, T = 20000, 30
+    classes = [LAGGED["bluerov2"], LAGGED["heavy"]]
+    cls = env_classes(E, "halves")
+    x0 = initial_state(E, 21, 91)
+    x0[19:, cls == 0] = 0
+    act = actions(T, 8, E, 92)
+    mult = param_multipliers(E, 0.2, 93)
+    a = _run(mgmod, classes, x0, act, 0.005, 4, env_class=cls, mult=mult)
+    b = _run(mgmod, classes, x0, act, 0.005, 4, env_class=cls, mult=mult)
+    for u, w in zip(a, b):
+        np.testing.assert_array_equal(u, w)
+
+
+def test_graph_replays_match_eager(mgmod):
+    """A captured rollout replayed several times, with eager work and synchronisation in
+    between, reproduces the eager result on every replay."""
+    E, T = 4096, 8
+    v = LAGGED["heavy"]
+    x0 = dev(initial_state(E, 21, 101))
+    a = dev(actions(T, 8, E, 102))
+    sim = mgmod.Sim(v, E, 0.005, 4)
+    traj = torch.empty((T, 21, E), device="cuda")
+    stats = torch.empty((T, 4), dtype=torch.float64, device="cuda")
+    sim.reset(state=x0)
+    sim.step(a, traj=traj, stats=stats)
+    ref_traj, ref_stats = traj.clone(), stats.clone()
+    for rep in range(3):
+        say("replay", rep)
+        traj.zero_()
+        stats.zero_()
+        sim.reset(state=x0)
+        sim.rollout(a, traj=traj, stats=stats)
+        torch.cuda.synchronize()
+        assert torch.equal(traj, ref_traj) and torch.equal(stats, ref_stats)
+        sim.reset(state=x0)
+        sim.step(a[:3])                  # eager work between replays
+        torch.cuda.synchronize()
+    sim.close()
+
+
+@pytest.mark.slow
+def test_c3_full_size_sampled(mgmod, oracle):
+    """2^20 mixed envs, 16 sub-steps per launch, 200 launches from a graph: sampled envs
+    against the oracle, every env finite with a unit quaternion, plain kernel identical."""
+    c = CONFIGS["c3"]
+    E = c.n_envs
+    classes = [LAGGED["bluerov2"], LAGGED["heavy"]]
+    cls = env_classes(E, "halves")
+    x0 = initial_state(E, 21, c.seed_base + 2)
+    x0[19:, cls == 0] = 0
+    mult = param_multipliers(E, c.rho, c.seed_base + 1)
+    sample = np.unique(np.concatenate([np.arange(0, E, 1024), [0, E // 2 - 1, E // 2, E - 1]]))
+    say("c3 generate actions")
+    act = torch.empty((c.n_ctrl, 8, E), dtype=torch.float32, device="cuda")
+    act_s = np.empty((c.n_ctrl, 8, len(sample)), np.float32)
+    for t, fr in enumerate(action_frames(c.n_ctrl, 8, E, c.seed_base + 3)):
+        act[t].copy_(torch.from_numpy(fr))
+        act_s[t] = fr[:, sample]
+    say("c3 fused graph rollout")
+    sim = mgmod.Sim(classes, E, c.dt_sub, c.substeps, env_class=cls)
+    sim.reset(state=dev(x0), param_mult=dev(mult))
+    stats = torch.empty((c.n_ctrl, 4), dtype=torch.float64, device="cuda")
+    sim.rollout(act, stats=stats)
+    xf = host(sim.get_state())
+    say("c3 plain graph rollout")
+    sim.reset(state=dev(x0), param_mult=dev(mult))
+    sim.rollout(act, plain=True)
+    xp = host(sim.get_state())
+    st = host(stats)
+    sim.close()
+    del act
+    np.testing.assert_array_equal(xp, xf)
+    assert np.isfinite(xf).all() and np.all(st[:, 3] == 0)
+    np.testing.assert_allclose(np.linalg.norm(xf[3:7], axis=0), 1.0, atol=1e-6)
+    ref = oracle.rollout(classes, x0[:, sample], act_s, c.substeps, c.dt_sub,
+                         env_class=cls[sample], mult=mult[:, sample])
+    assert rel_err(xf[:, sample], ref["x"]) <= TOL_TRAJ

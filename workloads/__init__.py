@@ -8,10 +8,11 @@ those from the raw numbers given here, each on its own.
 """
 from .presets import BLUEROV2, BLUEROV2_HEAVY, PARAM_NAMES, G0, vehicle_variant
 from .gen import (CONFIGS, WorkloadConfig, rng_for, param_multipliers, initial_state,
-                  actions, circle_waypoints, env_classes, euler_to_quat, random_states)
+                  actions, action_frames, circle_waypoints, env_classes, euler_to_quat,
+                  random_states)
 
 __all__ = [
     "BLUEROV2", "BLUEROV2_HEAVY", "PARAM_NAMES", "G0", "vehicle_variant",
     "CONFIGS", "WorkloadConfig", "rng_for", "param_multipliers", "initial_state",
-    "actions", "circle_waypoints", "env_classes", "euler_to_quat", "random_states",
+    "actions", "action_frames", "circle_waypoints", "env_classes", "euler_to_quat", "random_states",
 ]

@@ -29,20 +29,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "env-steps/s of batched Fossen RK4 step at 1M envs; served p50/p99 latency"
 PEAK_FP32_VALU = 157.3e12      # MI355X published FP32 vector peak (packed)
-PEAK_FP32_UNPACKED = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_HBM = 8.0e12
 
 
-def rhs_flops(n_thr, lag):
-    """Flops of one right-hand side as the kernel formulates it (FMA = 2)."""
-    return 160 + 12 * n_thr + (2 * n_thr if lag else 0)
-
-
-def substep_flops(n_thr, lag):
-    """Four right-hand sides, the RK4 combination (13 flops per state component) and
-    the quaternion renormalisation (12)."""
-    D = 13 + (n_thr if lag else 0)
-    return 4 * rhs_flops(n_thr, lag) + 13 * D + 12
+def substep_flops(n_thr, lag, substeps):
+    """Flops of one env-substep as the kernel formulates it (FMA = 2, one per add/mul):
+    four right-hand sides of the rigid-body states (158 each), the RK4 stages and
+    combination of the 13 rigid-body states (151), the quaternion renormalisation (12)
+    and, with a thruster lag, the closed-form lag stages (15 N + 36 - 12); plus the
+    per-control-step throttle map and command wrench (14 N - 6) spread over the sub-steps."""
+    core = 4 * 158 + 60 + 52 + 39 + 12
+    lag_part = (15 * n_thr + 36) if lag else 0
+    per_ctrl = 14 * n_thr - 6
+    return core + lag_part + per_ctrl / substeps
 
 
 def plain_bytes(n_thr, lag):
@@ -171,7 +170,7 @@ def main():
     torch.cuda.synchronize()
     fused_ms = ev0.elapsed_time(ev1) / reps
     launches = 2 * T
-    flops_rollout = (n_b * substep_flops(6, True) + n_h * substep_flops(8, True)) * T * S
+    flops_rollout = (n_b * substep_flops(6, True, S) + n_h * substep_flops(8, True, S)) * T * S
     achieved = flops_rollout / (fused_ms * 1e-3)
     st = stats.cpu().numpy()
 
@@ -192,9 +191,8 @@ def main():
                      "traffic": load_traffic("k_step_fused"),
                      "kernel": "k_step<6|8,lag> fused, 16 sub-steps per launch",
                      "avg_launch_us": fused_ms * 1e3 / launches,
-                     "flops_per_env_substep": {"bluerov2": substep_flops(6, True),
-                                               "heavy": substep_flops(8, True)},
-                     "frac_of_unpacked_fp32": achieved / PEAK_FP32_UNPACKED},
+                     "flops_per_env_substep": {"bluerov2": substep_flops(6, True, S),
+                                               "heavy": substep_flops(8, True, S)}},
         "stats_last_step": {"mean_dist": st[-1, 0] / max(1, E - st[-1, 3]),
                             "max_dist": st[-1, 1], "nonfinite": st[-1, 3]},
     }

@@ -34,29 +34,35 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src):
+def _compile(src, extra=()):
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [_hipcc(), "-c", *CFLAGS, src, "-o", obj]
+    cmd = [_hipcc(), "-c", *CFLAGS, *extra, src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose=True):
+def build(verbose=True, out=None, build_dir=None, defines=()):
+    """Compile and link; `out`/`build_dir`/`defines` allow side builds of tuning variants."""
+    global BUILD
+    if build_dir:
+        BUILD = build_dir
     os.makedirs(BUILD, exist_ok=True)
+    extra = [f"-D{d}" for d in defines]
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda f: _compile(f, extra), srcs))
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB} from {len(srcs)} sources")
-    return LIB
+        print(f"built {lib} from {len(srcs)} sources")
+    return lib
 
 
 if __name__ == "__main__":

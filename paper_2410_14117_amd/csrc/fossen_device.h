@@ -59,108 +59,150 @@ __device__ __forceinline__ void thrust_command(const ClassConst& cc, const float
   }
 }
 
-// x' = f(x).  xd may not alias x.
-template <int N, bool LAG>
-__device__ __forceinline__ void rhs(const float* x, float* xd, const EnvConst& P,
-                                    const ClassConst& cc, const float (&fcmd)[N]) {
-  const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
-  const float u = x[7], v = x[8], w = x[9], p = x[10], q = x[11], r = x[12];
-
-  // rotation body -> NED (unit-quaternion formula, stage quaternion as is)
-  const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
-  const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
-  const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
-  const float R00 = 1.0f - 2.0f * (yy + zz), R01 = 2.0f * (xy - wz), R02 = 2.0f * (xz + wy);
-  const float R10 = 2.0f * (xy + wz), R11 = 1.0f - 2.0f * (xx + zz), R12 = 2.0f * (yz - wx);
-  const float R20 = 2.0f * (xz - wy), R21 = 2.0f * (yz + wx), R22 = 1.0f - 2.0f * (xx + yy);
-
-  // kinematics
-  xd[0] = R00 * u + R01 * v + R02 * w;
-  xd[1] = R10 * u + R11 * v + R12 * w;
-  xd[2] = R20 * u + R21 * v + R22 * w;
-  const float hp = 0.5f * p, hq = 0.5f * q, hr = 0.5f * r;
-  xd[3] = -(qx * hp + qy * hq + qz * hr);
-  xd[4] = qw * hp + qy * hr - qz * hq;
-  xd[5] = qw * hq + qz * hp - qx * hr;
-  xd[6] = qw * hr + qx * hq - qy * hp;
-
-  // thrust -> body wrench
-  const float* th = LAG ? x + 13 : fcmd;
-  float tau[6];
+// Wrench of the commanded thrust, B f_cmd (once per control step).
+template <int N>
+__device__ __forceinline__ void command_wrench(const ClassConst& cc, const float (&fcmd)[N],
+                                               float (&gcmd)[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    float s = cc.B[k][0] * th[0];
+    float s = cc.B[k][0] * fcmd[0];
 #pragma unroll
-    for (int i = 1; i < N; ++i) s += cc.B[k][i] * th[i];
-    tau[k] = s;
-  }
-
-  // [a; b] = M nu
-  const float au = P.Muu * u + P.Muq * q, av = P.Mvv * v + P.Mvp * p, aw = P.Mww * w;
-  const float bp = P.Mvp * v + P.Mpp * p, bq = P.Muq * u + P.Mqq * q, br = P.Mrr * r;
-  // C(nu) nu = [w x a ; v x a + w x b]
-  const float c0 = q * aw - r * av;
-  const float c1 = r * au - p * aw;
-  const float c2 = p * av - q * au;
-  const float c3 = (v * aw - w * av) + (q * br - r * bq);
-  const float c4 = (w * au - u * aw) + (r * bp - p * br);
-  const float c5 = (u * av - v * au) + (p * bq - q * bp);
-  // D(nu) nu, diagonal linear + quadratic
-  const float d0 = (P.dl[0] + P.dq[0] * fabsf(u)) * u;
-  const float d1 = (P.dl[1] + P.dq[1] * fabsf(v)) * v;
-  const float d2 = (P.dl[2] + P.dq[2] * fabsf(w)) * w;
-  const float d3 = (P.dl[3] + P.dq[3] * fabsf(p)) * p;
-  const float d4 = (P.dl[4] + P.dq[4] * fabsf(q)) * q;
-  const float d5 = (P.dl[5] + P.dq[5] * fabsf(r)) * r;
-  // restoring g = -[(W-B) k ; h x k], k = R^T e3 = (R20, R21, R22), h = (0, 0, hz)
-  const float r0 = tau[0] - c0 - d0 + P.wmb * R20;
-  const float r1 = tau[1] - c1 - d1 + P.wmb * R21;
-  const float r2 = tau[2] - c2 - d2 + P.wmb * R22;
-  const float r3 = tau[3] - c3 - d3 - P.hz * R21;
-  const float r4 = tau[4] - c4 - d4 + P.hz * R20;
-  const float r5 = tau[5] - c5 - d5;
-  // nu' = M^-1 r
-  xd[7] = P.Iuu * r0 + P.Iuq * r4;
-  xd[8] = P.Ivv * r1 + P.Ivp * r3;
-  xd[9] = P.Iww * r2;
-  xd[10] = P.Ivp * r1 + P.Ipp * r3;
-  xd[11] = P.Iuq * r0 + P.Iqq * r4;
-  xd[12] = P.Irr * r5;
-  if constexpr (LAG) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) xd[13 + i] = (fcmd[i] - x[13 + i]) * cc.inv_tau;
+    for (int i = 1; i < N; ++i) s = fmaf(cc.B[k][i], fcmd[i], s);
+    gcmd[k] = s;
   }
 }
 
-// One classical RK4 sub-step (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6),
-// then q <- q / |q|.
+// Right-hand side of the 13 rigid-body states x = [p, q, nu] for a given
+// body wrench tau.  Written as fused multiply-add chains:
+//   p'  = R(q) v, as v + q_w t + q_v x t with t = 2 q_v x v (the same value as
+//         the unit-quaternion rotation matrix times v, for any q)
+//   xd[3..6] = q (x) (0, w)   -- TWICE q'; the caller applies the 1/2
+//   nu' = M^-1 (tau - C(nu) nu - D(nu) nu - g(q)),  with
+//         C(nu) nu = [w x a ; v x a + w x b], [a; b] = M nu (Kirchhoff form of
+//         the skew-symmetric C_RB + C_A), D diagonal linear + quadratic,
+//         g = -[(W-B) k ; h x k], k = R(q)^T e3, h = (0, 0, W z_g - B z_b).
+// xd may not alias x.
+__device__ __forceinline__ void rhs_core(const float* x, float* xd, const EnvConst& P,
+                                         const float (&tau)[6]) {
+  const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
+  const float u = x[7], v = x[8], w = x[9], p = x[10], q = x[11], r = x[12];
+
+  // kinematics
+  const float x2 = qx + qx, y2 = qy + qy, z2 = qz + qz;
+  const float t0 = fmaf(y2, w, -z2 * v);
+  const float t1 = fmaf(z2, u, -x2 * w);
+  const float t2 = fmaf(x2, v, -y2 * u);
+  xd[0] = fmaf(-qz, t1, fmaf(qy, t2, fmaf(qw, t0, u)));
+  xd[1] = fmaf(-qx, t2, fmaf(qz, t0, fmaf(qw, t1, v)));
+  xd[2] = fmaf(-qy, t0, fmaf(qx, t1, fmaf(qw, t2, w)));
+  xd[3] = -fmaf(qx, p, fmaf(qy, q, qz * r));
+  xd[4] = fmaf(-qz, q, fmaf(qy, r, qw * p));
+  xd[5] = fmaf(-qx, r, fmaf(qz, p, qw * q));
+  xd[6] = fmaf(-qy, p, fmaf(qx, q, qw * r));
+  // k = R^T e3, the third row of R(q)
+  const float k0 = fmaf(x2, qz, -y2 * qw);
+  const float k1 = fmaf(y2, qz, x2 * qw);
+  const float k2 = fmaf(-y2, qy, fmaf(-x2, qx, 1.0f));
+
+  // [a; b] = M nu
+  const float au = fmaf(P.Muq, q, P.Muu * u), av = fmaf(P.Mvp, p, P.Mvv * v), aw = P.Mww * w;
+  const float bp = fmaf(P.Mpp, p, P.Mvp * v), bq = fmaf(P.Mqq, q, P.Muq * u), br = P.Mrr * r;
+  // damping coefficients d_L + d_Q |nu|
+  const float e0 = fmaf(P.dq[0], fabsf(u), P.dl[0]);
+  const float e1 = fmaf(P.dq[1], fabsf(v), P.dl[1]);
+  const float e2 = fmaf(P.dq[2], fabsf(w), P.dl[2]);
+  const float e3 = fmaf(P.dq[3], fabsf(p), P.dl[3]);
+  const float e4 = fmaf(P.dq[4], fabsf(q), P.dl[4]);
+  const float e5 = fmaf(P.dq[5], fabsf(r), P.dl[5]);
+  // residual tau - C nu - D nu - g
+  const float r0 = fmaf(-e0, u, fmaf(P.wmb, k0, fmaf(-q, aw, fmaf(r, av, tau[0]))));
+  const float r1 = fmaf(-e1, v, fmaf(P.wmb, k1, fmaf(-r, au, fmaf(p, aw, tau[1]))));
+  const float r2 = fmaf(-e2, w, fmaf(P.wmb, k2, fmaf(-p, av, fmaf(q, au, tau[2]))));
+  const float r3 = fmaf(-e3, p, fmaf(-P.hz, k1,
+                   fmaf(r, bq, fmaf(-q, br, fmaf(w, av, fmaf(-v, aw, tau[3]))))));
+  const float r4 = fmaf(-e4, q, fmaf(P.hz, k0,
+                   fmaf(p, br, fmaf(-r, bp, fmaf(u, aw, fmaf(-w, au, tau[4]))))));
+  const float r5 = fmaf(-e5, r, fmaf(q, bp, fmaf(-p, bq, fmaf(v, au, fmaf(-u, av, tau[5])))));
+  // nu' = M^-1 r
+  xd[7] = fmaf(P.Iuq, r4, P.Iuu * r0);
+  xd[8] = fmaf(P.Ivp, r3, P.Ivv * r1);
+  xd[9] = P.Iww * r2;
+  xd[10] = fmaf(P.Ipp, r3, P.Ivp * r1);
+  xd[11] = fmaf(P.Iqq, r4, P.Iuq * r0);
+  xd[12] = P.Irr * r5;
+}
+
+// One classical RK4 sub-step (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) of
+// the full state [p, q, nu, f], then q <- q / |q|.
+//
+// The thruster states enter only through the wrench B f and obey the linear
+// lag f' = (f_cmd - f) / tau with f_cmd held, so their RK4 stage values are
+// f_cmd + sigma_i (f - f_cmd) exactly (class constants), the stage wrenches
+// are B f_cmd + sigma_i B (f - f_cmd), and the sub-step maps f - f_cmd to
+// rho (f - f_cmd): the same discrete map as generic RK4 on the lag states,
+// with one allocation product per sub-step instead of four.  Without a lag
+// the wrench is the command wrench B f_cmd throughout.
 template <int N, bool LAG>
 __device__ __forceinline__ void rk4_substep(float* x, const EnvConst& P, const ClassConst& cc,
-                                            const float (&fcmd)[N], float dt) {
-  constexpr int D = Dims<N, LAG>::D;
+                                            const float (&fcmd)[N], const float (&gcmd)[6],
+                                            float dt) {
   const float h2 = 0.5f * dt, h6 = dt * (1.0f / 6.0f);
-  float k[D], X[D], acc[D];
-  rhs<N, LAG>(x, k, P, cc, fcmd);
+  float df[N], dg[6], tau[6];
+  if constexpr (LAG) {
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
+    for (int i = 0; i < N; ++i) df[i] = x[13 + i] - fcmd[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      float s = cc.B[k][0] * df[0];
+#pragma unroll
+      for (int i = 1; i < N; ++i) s = fmaf(cc.B[k][i], df[i], s);
+      dg[k] = s;
+      tau[k] = gcmd[k] + s;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) tau[k] = gcmd[k];
+  }
+  // stage / combination factors; the quaternion rows of rhs_core are 2 q'
+  auto fac = [](int i, float f) { return (i >= 3 && i < 7) ? 0.5f * f : f; };
+  float k[13], X[13], acc[13];
+  rhs_core(x, k, P, tau);
+#pragma unroll
+  for (int i = 0; i < 13; ++i) {
     acc[i] = k[i];
-    X[i] = x[i] + h2 * k[i];
+    X[i] = fmaf(fac(i, h2), k[i], x[i]);
   }
-  rhs<N, LAG>(X, k, P, cc, fcmd);
+  if constexpr (LAG) {
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    acc[i] += 2.0f * k[i];
-    X[i] = x[i] + h2 * k[i];
+    for (int j = 0; j < 6; ++j) tau[j] = fmaf(cc.sigma2, dg[j], gcmd[j]);
   }
-  rhs<N, LAG>(X, k, P, cc, fcmd);
+  rhs_core(X, k, P, tau);
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    acc[i] += 2.0f * k[i];
-    X[i] = x[i] + dt * k[i];
+  for (int i = 0; i < 13; ++i) {
+    acc[i] = fmaf(2.0f, k[i], acc[i]);
+    X[i] = fmaf(fac(i, h2), k[i], x[i]);
   }
-  rhs<N, LAG>(X, k, P, cc, fcmd);
+  if constexpr (LAG) {
 #pragma unroll
-  for (int i = 0; i < D; ++i) x[i] += h6 * (acc[i] + k[i]);
+    for (int j = 0; j < 6; ++j) tau[j] = fmaf(cc.sigma3, dg[j], gcmd[j]);
+  }
+  rhs_core(X, k, P, tau);
+#pragma unroll
+  for (int i = 0; i < 13; ++i) {
+    acc[i] = fmaf(2.0f, k[i], acc[i]);
+    X[i] = fmaf(fac(i, dt), k[i], x[i]);
+  }
+  if constexpr (LAG) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) tau[j] = fmaf(cc.sigma4, dg[j], gcmd[j]);
+  }
+  rhs_core(X, k, P, tau);
+#pragma unroll
+  for (int i = 0; i < 13; ++i) x[i] = fmaf(fac(i, h6), acc[i] + k[i], x[i]);
+  if constexpr (LAG) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[13 + i] = fmaf(cc.rho, df[i], fcmd[i]);
+  }
   const float n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
   const float inv = rsqrtf(n2);
   x[3] *= inv;

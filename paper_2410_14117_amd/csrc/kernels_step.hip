@@ -43,8 +43,17 @@ __device__ __forceinline__ void block_stats(double s_dist, double m_dist, double
 // (the per-sub-step comparator whose state round-trips HBM).
 // ---------------------------------------------------------------------------
 
+#ifndef MG_STEP_WAVES_PER_EU
+#define MG_STEP_WAVES_PER_EU 0
+#endif
+#if MG_STEP_WAVES_PER_EU > 0
+#define MG_STEP_ATTR __attribute__((amdgpu_waves_per_eu(MG_STEP_WAVES_PER_EU)))
+#else
+#define MG_STEP_ATTR
+#endif
+
 template <int N, bool LAG, bool PLAIN>
-__global__ void __launch_bounds__(kBlock) k_step(const StepArgs a, const ClassConst cc) {
+__global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, const ClassConst cc) {
   constexpr int D = Dims<N, LAG>::D;
   const int n_ctrl = PLAIN ? 1 : a.n_ctrl;
   const int substeps = PLAIN ? 1 : a.substeps;
@@ -64,11 +73,12 @@ __global__ void __launch_bounds__(kBlock) k_step(const StepArgs a, const ClassCo
     double s_dist = 0.0, m_dist = 0.0, s_ke = 0.0, n_bad = 0.0;
     if (active) {
       const float* af = a.actions + (int64_t)t * a.n_max * a.E + c;
-      float act[N], fcmd[N];
+      float act[N], fcmd[N], gcmd[6];
 #pragma unroll
       for (int i = 0; i < N; ++i) act[i] = af[i * a.E];
       thrust_command<N>(cc, act, fcmd);
-      for (int s = 0; s < substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, a.dt);
+      command_wrench<N>(cc, fcmd, gcmd);
+      for (int s = 0; s < substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, a.dt);
       if (a.traj) {
         float* tf = a.traj + (int64_t)t * a.D * a.E + c;
 #pragma unroll

@@ -33,6 +33,11 @@ struct ClassConst {
   float B[6][kMaxThr];   // allocation matrix
   float f_max;
   float inv_tau;         // 1 / thruster lag (0 if none)
+  // Classical RK4 applied to the linear lag f' = (f_cmd - f) / tau with the
+  // command held: with z = dt / tau the stage values are
+  //   f_cmd + sigma_i (f - f_cmd),  sigma = 1, 1 - z/2, 1 - z/2 + z^2/4, 1 - z + z^2/2 - z^3/4
+  // and one sub-step maps f - f_cmd to rho (f - f_cmd), rho = 1 - z + z^2/2 - z^3/6 + z^4/24.
+  float sigma2, sigma3, sigma4, rho;
   int32_t n_thr;
   int32_t thr_map;       // 0 linear, 1 quadratic
   int32_t lag;

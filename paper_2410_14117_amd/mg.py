@@ -10,7 +10,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmg.so")
+LIB_PATH = os.environ.get("MG_LIBRARY") or os.path.join(HERE, "libmg.so")
 
 MG_ABI_VERSION = 1
 MAX_THR = 8

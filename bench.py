@@ -98,6 +98,55 @@ def cpu_baseline(n_envs=8192, n_ctrl=200):
                       f"{c.substeps} RK4 sub-steps, FP64, with statistics; {dt:.2f} s"}
 
 
+def bench_adjoint(torch, mg, reps=5):
+    """C4: 8192 BlueROV2 envs, 64 control steps of 10 ms, checkpoint every 8; forward with
+    checkpoints, backward (recompute + reverse sweep), against the plain per-step launch."""
+    from workloads import BLUEROV2, CONFIGS, initial_state, actions
+    c = CONFIGS["c4"]
+    E, T, K = c.n_envs, c.n_ctrl, c.extra["ckpt_every"]
+    dev = torch.device("cuda:0")
+    x0 = torch.from_numpy(initial_state(E, 13, c.seed_base + 2)).to(dev)
+    act = torch.from_numpy(actions(T, 6, E, c.seed_base + 3)).to(dev)
+    g = torch.randn((T, 13, E), generator=torch.Generator(device=dev).manual_seed(4),
+                    device=dev)
+    sim = mg.Sim(BLUEROV2, E, c.dt_sub, c.substeps)
+    traj = torch.empty((T, 13, E), device=dev)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    ckpt = [None]
+
+    def fwd():
+        sim.set_state(x0)
+        ckpt[0], _ = sim.adj_forward(act, K, traj=traj)
+
+    t_fwd = timed(fwd)
+    t_bwd = timed(lambda: sim.adj_backward(ckpt[0], act, K, g))
+
+    def plain():
+        sim.set_state(x0)
+        sim.rollout(act, plain=True)
+
+    t_plain = timed(plain)
+    sim.close()
+    return {"workload": "c4: 8192 BlueROV2 envs, 64 control steps of 10 ms, checkpoint every 8, "
+                        "gradients w.r.t. throttles, 19 hydrodynamic parameters and x0",
+            "forward_ms": t_fwd, "backward_ms": t_bwd, "fwd_plus_bwd_ms": t_fwd + t_bwd,
+            "cost_vs_forward": (t_fwd + t_bwd) / t_fwd,
+            "plain_forward_ms": t_plain, "cost_vs_plain_forward": (t_fwd + t_bwd) / t_plain,
+            "gradients_per_s": E / ((t_fwd + t_bwd) * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +156,7 @@ def main():
     ap.add_argument("--n-ctrl", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the environments are independent and this "
@@ -220,6 +270,8 @@ def main():
     del act
     torch.cuda.empty_cache()
 
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(torch, mg)
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline()
     print(json.dumps(out), flush=True)
 

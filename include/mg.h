@@ -172,6 +172,36 @@ mg_status mg_get_params(mg_sim* sim, float* out, int32_t out_on_device);
 /* Waits for the sim's stream; returns MG_ERR_DEVICE if queued work failed. */
 mg_status mg_synchronize(mg_sim* sim);
 
+/* ---- discrete adjoint of a rollout -------------------------------------------------
+ * The reverse mode of the exact discrete map mg_step computes (RK4 stages,
+ * quaternion renormalisation, thruster lag and clamp), for gradient-based use
+ * of the parallel environments of Sec. II.  Gradients are taken with respect
+ * to the throttles, the initial state and the hydrodynamic parameters theta =
+ * (M_A(6), D_L(6), D_Q(6), B) in absolute units (rows 4..22 of the 23-row
+ * parameter layout); the sim's current parameters are used.
+ *
+ * mg_adj_forward: T control steps from the sim's current state (which it
+ *   advances), one launch per class, storing the state before every
+ *   ckpt_every-th control step.
+ *   actions  device [T][N_max][E]
+ *   ckpt     device [ceil(T / ckpt_every)][D][E]  (written)
+ *   traj     device [T][D][E] state after each control step, or NULL
+ * mg_adj_backward: given dL/d traj, recomputes each segment of ckpt_every
+ *   control steps from its checkpoint (memory O(T / ckpt_every) states plus
+ *   one segment of sub-steps, held in a scratch buffer the sim owns) and
+ *   sweeps it backwards.
+ *   ckpt, actions  as written / read by mg_adj_forward with the same T, ckpt_every
+ *   dL_dtraj  device [T][D][E]
+ *   dL_dact   device [T][N_max][E]  (written; rows >= a class's n_thr are 0,
+ *             and so is the derivative of a clamped throttle)
+ *   dL_dtheta device [19][E]        (written)
+ *   dL_dx0    device [D][E] or NULL (written) */
+mg_status mg_adj_forward(mg_sim* sim, const float* actions, int32_t T, int32_t ckpt_every,
+                         float* ckpt, float* traj);
+mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, int32_t T,
+                          int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
+                          float* dL_dtheta, float* dL_dx0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,13 +14,23 @@
 
 namespace mg {
 
+// Scalar helpers; the double versions serve host-side checks of the kernel math.
+__host__ __device__ inline float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ inline double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__host__ __device__ inline float abs_t(float a) { return fabsf(a); }
+__host__ __device__ inline double abs_t(double a) { return fabs(a); }
+__device__ inline float rsqrt_t(float a) { return rsqrtf(a); }
+__host__ __device__ inline double rsqrt_t(double a) { return 1.0 / sqrt(a); }
+
 // Per-env constants held in registers for the whole launch.
-struct EnvConst {
-  float Muu, Mvv, Mww, Mpp, Mqq, Mrr, Muq, Mvp;
-  float Iuu, Ivv, Iww, Ipp, Iqq, Irr, Iuq, Ivp;
-  float dl[6], dq[6];
-  float wmb, hz;
+template <class T>
+struct EnvConstT {
+  T Muu, Mvv, Mww, Mpp, Mqq, Mrr, Muq, Mvp;
+  T Iuu, Ivv, Iww, Ipp, Iqq, Irr, Iuq, Ivp;
+  T dl[6], dq[6];
+  T wmb, hz;
 };
+using EnvConst = EnvConstT<float>;
 
 __device__ __forceinline__ EnvConst load_env_const(const float* __restrict__ der, int64_t Ep,
                                                    int64_t j) {
@@ -48,26 +58,26 @@ struct Dims {
 
 // Commanded thrust from a throttle frame (Eq. (3)): clamp to [-1,1], then
 // f_max a (linear) or f_max a|a| (quadratic).
-template <int N>
-__device__ __forceinline__ void thrust_command(const ClassConst& cc, const float (&a)[N],
-                                               float (&fcmd)[N]) {
+template <int N, class T>
+__host__ __device__ __forceinline__ void thrust_command(const ClassConst& cc, const T (&a)[N],
+                                                        T (&fcmd)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     // fminf/fmaxf would turn a NaN throttle into a number; keep NaN flowing
-    float ai = a[i] > 1.0f ? 1.0f : (a[i] < -1.0f ? -1.0f : a[i]);
-    fcmd[i] = cc.thr_map ? cc.f_max * ai * fabsf(ai) : cc.f_max * ai;
+    T ai = a[i] > T(1) ? T(1) : (a[i] < T(-1) ? T(-1) : a[i]);
+    fcmd[i] = cc.thr_map ? T(cc.f_max) * ai * abs_t(ai) : T(cc.f_max) * ai;
   }
 }
 
 // Wrench of the commanded thrust, B f_cmd (once per control step).
-template <int N>
-__device__ __forceinline__ void command_wrench(const ClassConst& cc, const float (&fcmd)[N],
-                                               float (&gcmd)[6]) {
+template <int N, class T>
+__host__ __device__ __forceinline__ void command_wrench(const ClassConst& cc, const T (&fcmd)[N],
+                                                        T (&gcmd)[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    float s = cc.B[k][0] * fcmd[0];
+    T s = T(cc.B[k][0]) * fcmd[0];
 #pragma unroll
-    for (int i = 1; i < N; ++i) s = fmaf(cc.B[k][i], fcmd[i], s);
+    for (int i = 1; i < N; ++i) s = fma_t(T(cc.B[k][i]), fcmd[i], s);
     gcmd[k] = s;
   }
 }
@@ -82,53 +92,54 @@ __device__ __forceinline__ void command_wrench(const ClassConst& cc, const float
 //         the skew-symmetric C_RB + C_A), D diagonal linear + quadratic,
 //         g = -[(W-B) k ; h x k], k = R(q)^T e3, h = (0, 0, W z_g - B z_b).
 // xd may not alias x.
-__device__ __forceinline__ void rhs_core(const float* x, float* xd, const EnvConst& P,
-                                         const float (&tau)[6]) {
-  const float qw = x[3], qx = x[4], qy = x[5], qz = x[6];
-  const float u = x[7], v = x[8], w = x[9], p = x[10], q = x[11], r = x[12];
+template <class T>
+__host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvConstT<T>& P,
+                                                  const T (&tau)[6]) {
+  const T qw = x[3], qx = x[4], qy = x[5], qz = x[6];
+  const T u = x[7], v = x[8], w = x[9], p = x[10], q = x[11], r = x[12];
 
   // kinematics
-  const float x2 = qx + qx, y2 = qy + qy, z2 = qz + qz;
-  const float t0 = fmaf(y2, w, -z2 * v);
-  const float t1 = fmaf(z2, u, -x2 * w);
-  const float t2 = fmaf(x2, v, -y2 * u);
-  xd[0] = fmaf(-qz, t1, fmaf(qy, t2, fmaf(qw, t0, u)));
-  xd[1] = fmaf(-qx, t2, fmaf(qz, t0, fmaf(qw, t1, v)));
-  xd[2] = fmaf(-qy, t0, fmaf(qx, t1, fmaf(qw, t2, w)));
-  xd[3] = -fmaf(qx, p, fmaf(qy, q, qz * r));
-  xd[4] = fmaf(-qz, q, fmaf(qy, r, qw * p));
-  xd[5] = fmaf(-qx, r, fmaf(qz, p, qw * q));
-  xd[6] = fmaf(-qy, p, fmaf(qx, q, qw * r));
+  const T x2 = qx + qx, y2 = qy + qy, z2 = qz + qz;
+  const T t0 = fma_t(y2, w, -z2 * v);
+  const T t1 = fma_t(z2, u, -x2 * w);
+  const T t2 = fma_t(x2, v, -y2 * u);
+  xd[0] = fma_t(-qz, t1, fma_t(qy, t2, fma_t(qw, t0, u)));
+  xd[1] = fma_t(-qx, t2, fma_t(qz, t0, fma_t(qw, t1, v)));
+  xd[2] = fma_t(-qy, t0, fma_t(qx, t1, fma_t(qw, t2, w)));
+  xd[3] = -fma_t(qx, p, fma_t(qy, q, qz * r));
+  xd[4] = fma_t(-qz, q, fma_t(qy, r, qw * p));
+  xd[5] = fma_t(-qx, r, fma_t(qz, p, qw * q));
+  xd[6] = fma_t(-qy, p, fma_t(qx, q, qw * r));
   // k = R^T e3, the third row of R(q)
-  const float k0 = fmaf(x2, qz, -y2 * qw);
-  const float k1 = fmaf(y2, qz, x2 * qw);
-  const float k2 = fmaf(-y2, qy, fmaf(-x2, qx, 1.0f));
+  const T k0 = fma_t(x2, qz, -y2 * qw);
+  const T k1 = fma_t(y2, qz, x2 * qw);
+  const T k2 = fma_t(-y2, qy, fma_t(-x2, qx, T(1)));
 
   // [a; b] = M nu
-  const float au = fmaf(P.Muq, q, P.Muu * u), av = fmaf(P.Mvp, p, P.Mvv * v), aw = P.Mww * w;
-  const float bp = fmaf(P.Mpp, p, P.Mvp * v), bq = fmaf(P.Mqq, q, P.Muq * u), br = P.Mrr * r;
+  const T au = fma_t(P.Muq, q, P.Muu * u), av = fma_t(P.Mvp, p, P.Mvv * v), aw = P.Mww * w;
+  const T bp = fma_t(P.Mpp, p, P.Mvp * v), bq = fma_t(P.Mqq, q, P.Muq * u), br = P.Mrr * r;
   // damping coefficients d_L + d_Q |nu|
-  const float e0 = fmaf(P.dq[0], fabsf(u), P.dl[0]);
-  const float e1 = fmaf(P.dq[1], fabsf(v), P.dl[1]);
-  const float e2 = fmaf(P.dq[2], fabsf(w), P.dl[2]);
-  const float e3 = fmaf(P.dq[3], fabsf(p), P.dl[3]);
-  const float e4 = fmaf(P.dq[4], fabsf(q), P.dl[4]);
-  const float e5 = fmaf(P.dq[5], fabsf(r), P.dl[5]);
+  const T e0 = fma_t(P.dq[0], abs_t(u), P.dl[0]);
+  const T e1 = fma_t(P.dq[1], abs_t(v), P.dl[1]);
+  const T e2 = fma_t(P.dq[2], abs_t(w), P.dl[2]);
+  const T e3 = fma_t(P.dq[3], abs_t(p), P.dl[3]);
+  const T e4 = fma_t(P.dq[4], abs_t(q), P.dl[4]);
+  const T e5 = fma_t(P.dq[5], abs_t(r), P.dl[5]);
   // residual tau - C nu - D nu - g
-  const float r0 = fmaf(-e0, u, fmaf(P.wmb, k0, fmaf(-q, aw, fmaf(r, av, tau[0]))));
-  const float r1 = fmaf(-e1, v, fmaf(P.wmb, k1, fmaf(-r, au, fmaf(p, aw, tau[1]))));
-  const float r2 = fmaf(-e2, w, fmaf(P.wmb, k2, fmaf(-p, av, fmaf(q, au, tau[2]))));
-  const float r3 = fmaf(-e3, p, fmaf(-P.hz, k1,
-                   fmaf(r, bq, fmaf(-q, br, fmaf(w, av, fmaf(-v, aw, tau[3]))))));
-  const float r4 = fmaf(-e4, q, fmaf(P.hz, k0,
-                   fmaf(p, br, fmaf(-r, bp, fmaf(u, aw, fmaf(-w, au, tau[4]))))));
-  const float r5 = fmaf(-e5, r, fmaf(q, bp, fmaf(-p, bq, fmaf(v, au, fmaf(-u, av, tau[5])))));
+  const T r0 = fma_t(-e0, u, fma_t(P.wmb, k0, fma_t(-q, aw, fma_t(r, av, tau[0]))));
+  const T r1 = fma_t(-e1, v, fma_t(P.wmb, k1, fma_t(-r, au, fma_t(p, aw, tau[1]))));
+  const T r2 = fma_t(-e2, w, fma_t(P.wmb, k2, fma_t(-p, av, fma_t(q, au, tau[2]))));
+  const T r3 = fma_t(-e3, p, fma_t(-P.hz, k1,
+                   fma_t(r, bq, fma_t(-q, br, fma_t(w, av, fma_t(-v, aw, tau[3]))))));
+  const T r4 = fma_t(-e4, q, fma_t(P.hz, k0,
+                   fma_t(p, br, fma_t(-r, bp, fma_t(u, aw, fma_t(-w, au, tau[4]))))));
+  const T r5 = fma_t(-e5, r, fma_t(q, bp, fma_t(-p, bq, fma_t(v, au, fma_t(-u, av, tau[5])))));
   // nu' = M^-1 r
-  xd[7] = fmaf(P.Iuq, r4, P.Iuu * r0);
-  xd[8] = fmaf(P.Ivp, r3, P.Ivv * r1);
+  xd[7] = fma_t(P.Iuq, r4, P.Iuu * r0);
+  xd[8] = fma_t(P.Ivp, r3, P.Ivv * r1);
   xd[9] = P.Iww * r2;
-  xd[10] = fmaf(P.Ipp, r3, P.Ivp * r1);
-  xd[11] = fmaf(P.Iqq, r4, P.Iuq * r0);
+  xd[10] = fma_t(P.Ipp, r3, P.Ivp * r1);
+  xd[11] = fma_t(P.Iqq, r4, P.Iuq * r0);
   xd[12] = P.Irr * r5;
 }
 
@@ -142,20 +153,20 @@ __device__ __forceinline__ void rhs_core(const float* x, float* xd, const EnvCon
 // rho (f - f_cmd): the same discrete map as generic RK4 on the lag states,
 // with one allocation product per sub-step instead of four.  Without a lag
 // the wrench is the command wrench B f_cmd throughout.
-template <int N, bool LAG>
-__device__ __forceinline__ void rk4_substep(float* x, const EnvConst& P, const ClassConst& cc,
-                                            const float (&fcmd)[N], const float (&gcmd)[6],
-                                            float dt) {
-  const float h2 = 0.5f * dt, h6 = dt * (1.0f / 6.0f);
-  float df[N], dg[6], tau[6];
+template <int N, bool LAG, class T>
+__host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P,
+                                                     const ClassConst& cc, const T (&fcmd)[N],
+                                                     const T (&gcmd)[6], T dt) {
+  const T h2 = T(0.5) * dt, h6 = dt * (T(1) / T(6));
+  T df[N], dg[6], tau[6];
   if constexpr (LAG) {
 #pragma unroll
     for (int i = 0; i < N; ++i) df[i] = x[13 + i] - fcmd[i];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      float s = cc.B[k][0] * df[0];
+      T s = T(cc.B[k][0]) * df[0];
 #pragma unroll
-      for (int i = 1; i < N; ++i) s = fmaf(cc.B[k][i], df[i], s);
+      for (int i = 1; i < N; ++i) s = fma_t(T(cc.B[k][i]), df[i], s);
       dg[k] = s;
       tau[k] = gcmd[k] + s;
     }
@@ -164,47 +175,47 @@ __device__ __forceinline__ void rk4_substep(float* x, const EnvConst& P, const C
     for (int k = 0; k < 6; ++k) tau[k] = gcmd[k];
   }
   // stage / combination factors; the quaternion rows of rhs_core are 2 q'
-  auto fac = [](int i, float f) { return (i >= 3 && i < 7) ? 0.5f * f : f; };
-  float k[13], X[13], acc[13];
+  auto fac = [](int i, T f) { return (i >= 3 && i < 7) ? T(0.5) * f : f; };
+  T k[13], X[13], acc[13];
   rhs_core(x, k, P, tau);
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
     acc[i] = k[i];
-    X[i] = fmaf(fac(i, h2), k[i], x[i]);
+    X[i] = fma_t(fac(i, h2), k[i], x[i]);
   }
   if constexpr (LAG) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) tau[j] = fmaf(cc.sigma2, dg[j], gcmd[j]);
+    for (int j = 0; j < 6; ++j) tau[j] = fma_t(T(cc.sigma2), dg[j], gcmd[j]);
   }
   rhs_core(X, k, P, tau);
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
-    acc[i] = fmaf(2.0f, k[i], acc[i]);
-    X[i] = fmaf(fac(i, h2), k[i], x[i]);
+    acc[i] = fma_t(T(2), k[i], acc[i]);
+    X[i] = fma_t(fac(i, h2), k[i], x[i]);
   }
   if constexpr (LAG) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) tau[j] = fmaf(cc.sigma3, dg[j], gcmd[j]);
+    for (int j = 0; j < 6; ++j) tau[j] = fma_t(T(cc.sigma3), dg[j], gcmd[j]);
   }
   rhs_core(X, k, P, tau);
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
-    acc[i] = fmaf(2.0f, k[i], acc[i]);
-    X[i] = fmaf(fac(i, dt), k[i], x[i]);
+    acc[i] = fma_t(T(2), k[i], acc[i]);
+    X[i] = fma_t(fac(i, dt), k[i], x[i]);
   }
   if constexpr (LAG) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) tau[j] = fmaf(cc.sigma4, dg[j], gcmd[j]);
+    for (int j = 0; j < 6; ++j) tau[j] = fma_t(T(cc.sigma4), dg[j], gcmd[j]);
   }
   rhs_core(X, k, P, tau);
 #pragma unroll
-  for (int i = 0; i < 13; ++i) x[i] = fmaf(fac(i, h6), acc[i] + k[i], x[i]);
+  for (int i = 0; i < 13; ++i) x[i] = fma_t(fac(i, h6), acc[i] + k[i], x[i]);
   if constexpr (LAG) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[13 + i] = fmaf(cc.rho, df[i], fcmd[i]);
+    for (int i = 0; i < N; ++i) x[13 + i] = fma_t(T(cc.rho), df[i], fcmd[i]);
   }
-  const float n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
-  const float inv = rsqrtf(n2);
+  const T n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
+  const T inv = rsqrt_t(n2);
   x[3] *= inv;
   x[4] *= inv;
   x[5] *= inv;

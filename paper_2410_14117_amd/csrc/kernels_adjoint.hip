@@ -1,0 +1,156 @@
+// kernels_adjoint.hip -- discrete adjoint of a T-control-step rollout with
+// segment checkpointing.
+//
+//   k_adj_fwd : T control steps in one launch (state in registers); stores the
+//               state before every ckpt_every-th step and, optionally, the
+//               trajectory.
+//   k_adj_bwd : one lane per env walks the segments last to first: recomputes
+//               the segment's sub-step states from its checkpoint into a
+//               scratch buffer, then sweeps the sub-step VJPs backwards,
+//               emitting dL/d throttle per step and accumulating dL/d theta.
+#include "fossen_adjoint.h"
+
+namespace mg {
+
+template <int N>
+__device__ __forceinline__ void load_command(const ClassConst& cc, const AdjArgs& a, int t,
+                                             int64_t c, float (&act)[N], float (&fcmd)[N],
+                                             float (&gcmd)[6]) {
+  const float* af = a.actions + (int64_t)t * a.n_max * a.E + c;
+#pragma unroll
+  for (int i = 0; i < N; ++i) act[i] = af[i * a.E];
+  thrust_command<N>(cc, act, fcmd);
+  command_wrench<N>(cc, fcmd, gcmd);
+}
+
+template <int N, bool LAG>
+__global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const ClassConst cc) {
+  constexpr int D = Dims<N, LAG>::D;
+  const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (local >= a.seg_len) return;
+  const int64_t j = a.seg_start + local;
+  const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
+  float x[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) x[i] = a.state[i * a.Ep + j];
+  const EnvConst P = load_env_const(a.derived, a.Ep, j);
+  for (int t = 0; t < a.T; ++t) {
+    if (t % a.ckpt_every == 0) {
+      float* ck = a.ckpt + (int64_t)(t / a.ckpt_every) * a.D * a.E + c;
+#pragma unroll
+      for (int i = 0; i < D; ++i) ck[i * a.E] = x[i];
+      for (int i = D; i < a.D; ++i) ck[i * a.E] = 0.0f;
+    }
+    float act[N], fcmd[N], gcmd[6];
+    load_command<N>(cc, a, t, c, act, fcmd, gcmd);
+    for (int s = 0; s < a.substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, a.dt);
+    if (a.traj) {
+      float* tf = a.traj + (int64_t)t * a.D * a.E + c;
+#pragma unroll
+      for (int i = 0; i < D; ++i) tf[i * a.E] = x[i];
+      for (int i = D; i < a.D; ++i) tf[i * a.E] = 0.0f;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) a.state[i * a.Ep + j] = x[i];
+}
+
+template <int N, bool LAG>
+__global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const ClassConst cc) {
+  constexpr int D = Dims<N, LAG>::D;
+  const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (local >= a.seg_len) return;
+  const int64_t j = a.seg_start + local;
+  const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
+  const EnvConst P = load_env_const(a.derived, a.Ep, j);
+  const int K = a.ckpt_every, S = a.substeps;
+  const int nseg = (a.T + K - 1) / K;
+  float lam[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) lam[i] = 0.0f;
+  ThetaBar<float> thb;
+  theta_bar_zero(thb);
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int t0 = seg * K, t1 = min(a.T, t0 + K);
+    // recompute this segment's sub-step inputs from its checkpoint
+    float x[D];
+    const float* ck = a.ckpt + (int64_t)seg * a.D * a.E + c;
+#pragma unroll
+    for (int i = 0; i < D; ++i) x[i] = ck[i * a.E];
+    for (int t = t0; t < t1; ++t) {
+      float act[N], fcmd[N], gcmd[6];
+      load_command<N>(cc, a, t, c, act, fcmd, gcmd);
+      for (int s = 0; s < S; ++s) {
+        float* sb = a.segbuf + (int64_t)((t - t0) * S + s) * D * a.Ep + j;
+#pragma unroll
+        for (int i = 0; i < D; ++i) sb[i * a.Ep] = x[i];
+        rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, a.dt);
+      }
+    }
+    // reverse sweep over the segment
+    for (int t = t1 - 1; t >= t0; --t) {
+      const float* gt = a.gtraj + (int64_t)t * a.D * a.E + c;
+#pragma unroll
+      for (int i = 0; i < D; ++i) lam[i] += gt[i * a.E];
+      float act[N], fcmd[N], gcmd[6], fcb[N], gcb[6], ab[N];
+      load_command<N>(cc, a, t, c, act, fcmd, gcmd);
+#pragma unroll
+      for (int i = 0; i < N; ++i) fcb[i] = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) gcb[k] = 0.0f;
+      for (int s = S - 1; s >= 0; --s) {
+        float y[D];
+        const float* sb = a.segbuf + (int64_t)((t - t0) * S + s) * D * a.Ep + j;
+#pragma unroll
+        for (int i = 0; i < D; ++i) y[i] = sb[i * a.Ep];
+        rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
+      }
+      throttle_vjp<N>(cc, act, fcb, gcb, ab);
+      float* ga = a.gact + (int64_t)t * a.n_max * a.E + c;
+#pragma unroll
+      for (int i = 0; i < N; ++i) ga[i * a.E] = ab[i];
+      for (int i = N; i < a.n_max; ++i) ga[i * a.E] = 0.0f;
+    }
+  }
+  // theta = (M_A(6), D_L(6), D_Q(6), B);  W - B and h_z = W z_g - B z_b carry B
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    a.gtheta[i * a.E + c] = thb.ma[i];
+    a.gtheta[(6 + i) * a.E + c] = thb.dl[i];
+    a.gtheta[(12 + i) * a.E + c] = thb.dq[i];
+  }
+  a.gtheta[18 * a.E + c] = -thb.wmb - a.zb * thb.hz;
+  if (a.gx0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) a.gx0[i * a.E + c] = lam[i];
+    for (int i = D; i < a.D; ++i) a.gx0[i * a.E + c] = 0.0f;
+  }
+}
+
+template <int N, bool LAG>
+static hipError_t launch_adj_t(bool backward, const ClassConst& cc, const AdjArgs& a,
+                               hipStream_t s) {
+  const int64_t nblk = (a.seg_len + kBlock - 1) / kBlock;
+  if (nblk == 0) return hipSuccess;
+  if (backward)
+    hipLaunchKernelGGL((k_adj_bwd<N, LAG>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a, cc);
+  else
+    hipLaunchKernelGGL((k_adj_fwd<N, LAG>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a, cc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(bool backward, const ClassConst& cc, const AdjArgs& a, hipStream_t s) {
+  const bool lag = cc.lag != 0;
+#define MG_CASE(n)                                                                    \
+  case n:                                                                             \
+    return lag ? launch_adj_t<n, true>(backward, cc, a, s)                            \
+               : launch_adj_t<n, false>(backward, cc, a, s);
+  switch (cc.n_thr) {
+    MG_CASE(1) MG_CASE(2) MG_CASE(3) MG_CASE(4) MG_CASE(5) MG_CASE(6) MG_CASE(7) MG_CASE(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef MG_CASE
+}
+
+}  // namespace mg

@@ -86,6 +86,28 @@ struct ResetArgs {
   int32_t write_state;         // 0: keep the state
 };
 
+struct AdjArgs {
+  float* state;                // internal [D][Ep] (forward reads and advances it)
+  const float* derived;        // internal [kNumDerived][Ep]
+  int64_t Ep, E;
+  const int32_t* perm;
+  int64_t seg_start, seg_len;
+  const float* actions;        // caller [T][n_max][E]
+  int32_t n_max, D, T, substeps, ckpt_every;
+  float dt;
+  float* ckpt;                 // caller [ceil(T/K)][D][E]
+  float* traj;                 // caller [T][D][E] or NULL (forward)
+  const float* gtraj;          // caller [T][D][E] dL/d traj (backward)
+  float* gact;                 // caller [T][n_max][E]
+  float* gtheta;               // caller [19][E]
+  float* gx0;                  // caller [D][E] or NULL
+  float* segbuf;               // internal [K * S][Dc][Ep] scratch (Dc = class state width)
+  float zb;                    // class z_b (for dL/dB through h_z)
+};
+
+// launchers (kernels_adjoint.hip)
+hipError_t launch_adjoint(bool backward, const ClassConst& cc, const AdjArgs& a, hipStream_t s);
+
 // launchers (kernels_step.hip)
 hipError_t launch_step(const ClassConst& cc, const StepArgs& a, hipStream_t s);
 hipError_t launch_stats_finalize(const double* partials, int32_t nblk, int32_t n_ctrl,

@@ -57,6 +57,8 @@ struct mg_sim {
   double* partials = nullptr;
   size_t partials_cap = 0;     // doubles
   float* staging = nullptr;    // [max(D,23)][E] for host copies with a permuted layout
+  float* segbuf = nullptr;     // adjoint recomputation scratch
+  size_t segbuf_cap = 0;       // floats
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
@@ -312,6 +314,32 @@ mg_status step_common(mg_sim* s, const float* actions, int32_t n_ctrl, const flo
   return enqueue_steps(s, s->stream, actions, n_ctrl, targets, traj, stats, plain, false);
 }
 
+mg_status adj_common(mg_sim* s, const float* actions, int32_t T, int32_t K, const float* ckpt) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!actions || !ckpt) return fail(s, MG_ERR_INVALID, "actions and ckpt must not be NULL");
+  if (T < 1 || K < 1) return fail(s, MG_ERR_INVALID, "T and ckpt_every must be >= 1");
+  return MG_OK;
+}
+
+AdjArgs adj_args(mg_sim* s, const float* actions, int32_t T, int32_t K) {
+  AdjArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.state = s->state;
+  a.derived = s->derived;
+  a.Ep = s->Ep;
+  a.E = s->E;
+  a.perm = s->perm;
+  a.actions = actions;
+  a.n_max = s->n_max;
+  a.D = s->D;
+  a.T = T;
+  a.substeps = s->substeps;
+  a.ckpt_every = K;
+  a.dt = (float)s->dt;
+  return a;
+}
+
 }  // namespace
 
 extern "C" {
@@ -462,7 +490,7 @@ void mg_destroy(mg_sim* s) {
     clear_graphs(s);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     void* bufs[] = {s->state, s->params, s->derived, s->perm, s->iperm, s->class_of,
-                    s->nominal_dev, s->partials, s->staging};
+                    s->nominal_dev, s->partials, s->staging, s->segbuf};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     (void)hipGetLastError();
@@ -569,6 +597,59 @@ mg_status mg_get_params(mg_sim* s, float* out, int32_t out_on_device) {
   if (st) return st;
   DeviceGuard g(s->device);
   return copy_out(s, s->params, kNumParams, out, out_on_device);
+}
+
+mg_status mg_adj_forward(mg_sim* s, const float* actions, int32_t T, int32_t ckpt_every,
+                         float* ckpt, float* traj) {
+  mg_status st = adj_common(s, actions, T, ckpt_every, ckpt);
+  if (st) return st;
+  DeviceGuard g(s->device);
+  AdjArgs a = adj_args(s, actions, T, ckpt_every);
+  a.ckpt = ckpt;
+  a.traj = traj;
+  for (int k = 0; k < s->n_classes; ++k) {
+    a.seg_start = s->seg_start[k];
+    a.seg_len = s->seg_len[k];
+    MG_HIP(s, launch_adjoint(false, s->cc[k], a, s->stream));
+  }
+  return MG_OK;
+}
+
+mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* actions, int32_t T,
+                          int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
+                          float* dL_dtheta, float* dL_dx0) {
+  mg_status st = adj_common(s, actions, T, ckpt_every, ckpt);
+  if (st) return st;
+  if (!dL_dtraj || !dL_dact || !dL_dtheta)
+    return fail(s, MG_ERR_INVALID, "dL_dtraj, dL_dact and dL_dtheta must not be NULL");
+  DeviceGuard g(s->device);
+  const size_t need = (size_t)std::min(ckpt_every, T) * s->substeps * s->D * (size_t)s->Ep;
+  if (need > s->segbuf_cap) {
+    MG_HIP(s, hipStreamSynchronize(s->stream));
+    if (s->segbuf) MG_HIP(s, hipFree(s->segbuf));
+    s->segbuf = nullptr;
+    s->segbuf_cap = 0;
+    if (hipMalloc(&s->segbuf, need * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      s->segbuf = nullptr;
+      return fail(s, MG_ERR_OOM, "adjoint scratch allocation failed");
+    }
+    s->segbuf_cap = need;
+  }
+  AdjArgs a = adj_args(s, actions, T, ckpt_every);
+  a.ckpt = const_cast<float*>(ckpt);
+  a.gtraj = dL_dtraj;
+  a.gact = dL_dact;
+  a.gtheta = dL_dtheta;
+  a.gx0 = dL_dx0;
+  a.segbuf = s->segbuf;
+  for (int k = 0; k < s->n_classes; ++k) {
+    a.seg_start = s->seg_start[k];
+    a.seg_len = s->seg_len[k];
+    a.zb = (float)s->nominal[k].zb;
+    MG_HIP(s, launch_adjoint(true, s->cc[k], a, s->stream));
+  }
+  return MG_OK;
 }
 
 mg_status mg_synchronize(mg_sim* s) {

@@ -68,6 +68,9 @@ _SIGS = {
     "mg_get_state": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
     "mg_get_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
     "mg_synchronize": (ctypes.c_int32, [_vp]),
+    "mg_adj_forward": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
+    "mg_adj_backward": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                         _vp, _vp]),
 }
 
 _lib = None
@@ -264,3 +267,41 @@ class Sim:
 
     def synchronize(self):
         self._check(lib().mg_synchronize(self._h))
+
+    # -- adjoint ---------------------------------------------------------------------------
+    def adj_forward(self, actions, ckpt_every, ckpt=None, traj=None):
+        """Rollout of T = actions.shape[0] control steps from the current state, saving a
+        checkpoint before every ckpt_every-th step.  Returns (ckpt, traj)."""
+        import torch
+        T, E, D, N = int(actions.shape[0]), self.n_envs, self.state_dim, self.action_dim
+        K = int(ckpt_every)
+        if K < 1:
+            raise ValueError("ckpt_every must be >= 1")
+        nseg = (T + K - 1) // K
+        dev = f"cuda:{self.device}"
+        if ckpt is None:
+            ckpt = torch.empty((nseg, D, E), dtype=torch.float32, device=dev)
+        a = _ptr(actions, torch.float32, (T, N, E), "actions")
+        ck = _ptr(ckpt, torch.float32, (nseg, D, E), "ckpt")
+        tr = _ptr(traj, torch.float32, (T, D, E), "traj")
+        self._bind_stream()
+        self._check(lib().mg_adj_forward(self._h, a, T, K, ck, tr))
+        return ckpt, traj
+
+    def adj_backward(self, ckpt, actions, ckpt_every, dL_dtraj, want_x0=True):
+        """Returns (dL/d actions [T][N_max][E], dL/d theta [19][E], dL/d x0 [D][E] or None)."""
+        import torch
+        T, E, D, N = int(actions.shape[0]), self.n_envs, self.state_dim, self.action_dim
+        K = int(ckpt_every)
+        nseg = (T + K - 1) // K
+        dev = f"cuda:{self.device}"
+        gact = torch.empty((T, N, E), dtype=torch.float32, device=dev)
+        gth = torch.empty((NUM_THETA, E), dtype=torch.float32, device=dev)
+        gx0 = torch.empty((D, E), dtype=torch.float32, device=dev) if want_x0 else None
+        ck = _ptr(ckpt, torch.float32, (nseg, D, E), "ckpt")
+        a = _ptr(actions, torch.float32, (T, N, E), "actions")
+        g = _ptr(dL_dtraj, torch.float32, (T, D, E), "dL_dtraj")
+        self._bind_stream()
+        self._check(lib().mg_adj_backward(self._h, ck, a, T, K, g, gact.data_ptr(), gth.data_ptr(),
+                                          None if gx0 is None else gx0.data_ptr()))
+        return gact, gth, gx0

@@ -1,0 +1,200 @@
+"""GPU parity of the hand-written RK4 adjoint (mg_adj_forward / mg_adj_backward
+behind torch.autograd) against the oracle's FP64 dual-number gradient and FP64
+central finite differences.
+
+Tolerance: per env, ||g_gpu - g_ref||_2 / ||g_ref||_2 <= 1e-3 for each of the
+throttle, parameter and initial-state gradients.
+"""
+import numpy as np
+import pytest
+
+from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
+                       actions, param_multipliers, circle_waypoints, env_classes)
+from tests.gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL_GRAD = 1e-3
+
+
+@pytest.fixture(scope="module")
+def mgmod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_14117_amd import mg
+    mg.lib()
+    return mg
+
+
+def _nominal(v):
+    return np.array([v["mass"], *v["inertia"], *v["added_mass"], *v["d_lin"], *v["d_quad"],
+                     v["buoyancy"]])
+
+
+def _track_loss_torch(traj, pref, qref, lam=1.0):
+    """L = sum_e sum_t |p_t - p*_t|^2 + lam (1 - <q_t, q*_t>^2), in float64."""
+    t = traj.double()
+    dp = t[:, 0:3] - pref.double()
+    dot = (t[:, 3:7] * qref.double()).sum(dim=1)
+    return (dp * dp).sum() + lam * (1.0 - dot * dot).sum()
+
+
+def _rel(g, ref):
+    return np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-30)
+
+
+def _gpu_grads(mgmod, v, x0, act, mult, pref, qref, S, dt, K, classes=None, cls=None):
+    from paper_2410_14117_amd.autograd import rollout
+    E = x0.shape[1]
+    sim = mgmod.Sim(classes or v, E, dt, S, env_class=cls)
+    if classes is None:
+        params = (_nominal(v)[:, None] * mult.astype(np.float64)).astype(np.float32)
+    else:
+        params = np.stack([(_nominal(classes[c]) * mult[:, e].astype(np.float64)).astype(np.float32)
+                           for e, c in enumerate(cls)], axis=1)
+    x0_t = dev(x0).requires_grad_(True)
+    a_t = dev(act).requires_grad_(True)
+    hydro = dev(params[4:]).requires_grad_(True)
+    rigid = dev(params[:4])
+    traj = rollout(sim, x0_t, a_t, hydro, rigid, ckpt_every=K)
+    loss = _track_loss_torch(traj, dev(pref), dev(qref))
+    loss.backward()
+    torch.cuda.synchronize()
+    out = (float(loss), host(a_t.grad), host(hydro.grad), host(x0_t.grad), host(traj))
+    sim.close()
+    return out
+
+
+def test_c4_gradient_vs_dual_numbers_and_fd(mgmod, oracle):
+    """8192 BlueROV2 envs, 64 steps of 10 ms, checkpoint every 8: the 16-env sample
+    against the FP64 dual-number gradient and FP64 central finite differences."""
+    c = CONFIGS["c4"]
+    E, T, K = c.n_envs, c.n_ctrl, c.extra["ckpt_every"]
+    v = BLUEROV2
+    x0 = initial_state(E, 13, c.seed_base + 2)
+    act = actions(T, 6, E, c.seed_base + 3)
+    pref, qref = circle_waypoints(T, E, c.dt_sub, c.seed_base + 4, omega=c.extra["omega"])
+    mult = np.ones((23, E), np.float32)
+    say("c4 adjoint", E, T, K)
+    loss, g_act, g_th, g_x0, _ = _gpu_grads(mgmod, v, x0, act, mult, pref, qref, 1, c.dt_sub, K)
+    ref_loss_all = oracle.track_loss(v, x0, act, 1, c.dt_sub, pref, qref)
+    assert loss == pytest.approx(ref_loss_all.sum(), rel=1e-5)
+    sub = np.arange(16)
+    r_loss, r_act, r_th, r_x0 = oracle.track_loss_grad(
+        v, x0[:, sub], act[:, :, sub], 1, c.dt_sub, pref[:, :, sub], qref[:, :, sub],
+        mult=mult[:, sub], want_x0=True)
+    for k, e in enumerate(sub):
+        assert _rel(g_act[:, :, e], r_act[:, :, k]) <= TOL_GRAD
+        assert _rel(g_th[:, e], r_th[:, k]) <= TOL_GRAD
+        assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD
+    # FP64 central differences (h = 1e-6) of the oracle loss for the 19 parameters
+    h = 1e-6
+    nom = _nominal(v)[4:]
+    x0s, acts, prs, qrs = x0[:, sub], act[:, :, sub].astype(np.float64), pref[:, :, sub], qref[:, :, sub]
+    fd = np.zeros((19, 16))
+    for j in range(19):
+        mp = np.ones((23, 16))
+        mm = np.ones((23, 16))
+        mp[4 + j] += h / nom[j]
+        mm[4 + j] -= h / nom[j]
+        fd[j] = (oracle.track_loss(v, x0s, acts, 1, c.dt_sub, prs, qrs, mult=mp)
+                 - oracle.track_loss(v, x0s, acts, 1, c.dt_sub, prs, qrs, mult=mm)) / (2 * h)
+    for k, e in enumerate(sub):
+        assert _rel(g_th[:, e], fd[:, k]) <= TOL_GRAD
+    # and for a random subset of throttles
+    rng = np.random.default_rng(7)
+    for _ in range(24):
+        t, i = rng.integers(0, T), rng.integers(0, 6)
+        ap, am = acts.copy(), acts.copy()
+        ap[t, i] += h
+        am[t, i] -= h
+        fda = (oracle.track_loss(v, x0s, ap, 1, c.dt_sub, prs, qrs)
+               - oracle.track_loss(v, x0s, am, 1, c.dt_sub, prs, qrs)) / (2 * h)
+        np.testing.assert_allclose(g_act[t, i, sub], fda, rtol=2e-3,
+                                   atol=2e-3 * np.abs(r_act[:, :, :]).max())
+
+
+def test_heavy_lag_quadratic_substeps(mgmod, oracle):
+    """Thruster lag + quadratic map + 4 sub-steps + randomised parameters (ragged env count)."""
+    v = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
+    E, T, K = 300, 12, 5
+    x0 = initial_state(E, 21, 301)
+    x0[13:] = np.random.default_rng(302).uniform(-20, 20, size=(8, E)).astype(np.float32)
+    act = actions(T, 8, E, 303) * np.float32(1.2)          # some throttles clamp
+    mult = param_multipliers(E, 0.2, 304)
+    pref, qref = circle_waypoints(T, E, 0.02, 305)
+    say("heavy adjoint")
+    _, g_act, g_th, g_x0, _ = _gpu_grads(mgmod, v, x0, act, mult, pref, qref, 4, 0.005, K)
+    sub = np.arange(0, E, 19)
+    _, r_act, r_th, r_x0 = oracle.track_loss_grad(
+        v, x0[:, sub], act[:, :, sub], 4, 0.005, pref[:, :, sub], qref[:, :, sub],
+        mult=mult[:, sub], want_x0=True)
+    for k, e in enumerate(sub):
+        assert _rel(g_act[:, :, e], r_act[:, :, k]) <= TOL_GRAD
+        assert _rel(g_th[:, e], r_th[:, k]) <= TOL_GRAD
+        assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD
+    clamped = np.abs(act) > 1
+    assert np.all(g_act[clamped] == 0)
+
+
+def test_checkpoint_interval_invariance(mgmod):
+    """Recomputation from checkpoints is the forward code itself: gradients are bitwise equal
+    for checkpoints every 1, 8 and 64 steps."""
+    v = vehicle_variant(BLUEROV2, thr_map=1, thr_tau=0.05)
+    E, T = 512, 64
+    x0 = initial_state(E, 19, 311)
+    act = actions(T, 6, E, 312)
+    mult = param_multipliers(E, 0.2, 313)
+    pref, qref = circle_waypoints(T, E, 0.01, 314)
+    res = [_gpu_grads(mgmod, v, x0, act, mult, pref, qref, 2, 0.005, K) for K in (1, 8, 64)]
+    for r in res[1:]:
+        for a, b in zip(r[1:], res[0][1:]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_adjoint_forward_matches_step(mgmod):
+    """The adjoint's forward pass produces the same trajectory as mg_step (bitwise)."""
+    v = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
+    E, T = 700, 20
+    x0 = dev(initial_state(E, 21, 321))
+    a = dev(actions(T, 8, E, 322))
+    sim = mgmod.Sim(v, E, 0.005, 4)
+    sim.reset(state=x0)
+    tr1 = torch.empty((T, 21, E), device="cuda")
+    sim.step(a, traj=tr1)
+    sim.reset(state=x0)
+    tr2 = torch.empty((T, 21, E), device="cuda")
+    ckpt, _ = sim.adj_forward(a, 6, traj=tr2)
+    torch.cuda.synchronize()
+    assert torch.equal(tr1, tr2)
+    assert torch.equal(ckpt[0], x0)
+    assert torch.equal(ckpt[1], tr1[5])
+    sim.close()
+
+
+def test_mixed_classes_interleaved(mgmod, oracle):
+    vb = vehicle_variant(BLUEROV2, thr_map=1, thr_tau=0.05)
+    vh = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
+    E, T, K = 400, 10, 4
+    cls = env_classes(E, "bernoulli", 331)
+    x0 = initial_state(E, 21, 332)
+    x0[19:, cls == 0] = 0
+    act = actions(T, 8, E, 333)
+    mult = param_multipliers(E, 0.2, 334)
+    pref, qref = circle_waypoints(T, E, 0.02, 335)
+    say("mixed adjoint")
+    _, g_act, g_th, g_x0, _ = _gpu_grads(mgmod, None, x0, act, mult, pref, qref, 2, 0.01, K,
+                                         classes=[vb, vh], cls=cls)
+    for k, v in enumerate([vb, vh]):
+        sel = np.where(cls == k)[0][:12]
+        D = 13 + len(v["thr_pos"])
+        N = len(v["thr_pos"])
+        _, r_act, r_th, r_x0 = oracle.track_loss_grad(
+            v, x0[:D][:, sel], act[:, :N][:, :, sel], 2, 0.01, pref[:, :, sel], qref[:, :, sel],
+            mult=mult[:, sel], want_x0=True)
+        for kk, e in enumerate(sel):
+            assert _rel(g_act[:, :N, e], r_act[:, :, kk]) <= TOL_GRAD
+            assert np.all(g_act[:, N:, e] == 0)
+            assert _rel(g_th[:, e], r_th[:, kk]) <= TOL_GRAD
+            assert _rel(g_x0[:D, e], r_x0[:, kk]) <= TOL_GRAD

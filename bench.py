@@ -147,6 +147,92 @@ def bench_adjoint(torch, mg, reps=5):
             "gradients_per_s": E / ((t_fwd + t_bwd) * 1e-3)}
 
 
+def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005):
+    """C5: 32 clients with Poisson arrivals (2000 req/s aggregate), env counts log-uniform in
+    [16, 65536], half step requests (1 control step) and half rollouts (1..64 steps), mixed
+    BlueROV2 / Heavy (+-20 % randomisation, 4 RK4 sub-steps of 5 ms per control step),
+    inputs resident on the device; latency = arrival -> final states in host memory."""
+    import threading
+    from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
+                           actions, param_multipliers, env_classes)
+    c = CONFIGS["c5"]
+    classes = [vehicle_variant(BLUEROV2, thr_map=1, thr_tau=0.05),
+               vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)]
+    P, LMAX, D = 1 << 17, 64, 21
+    dev = torch.device("cuda:0")
+    cls = env_classes(P, "bernoulli", c.seed_base + 5)
+    x0 = initial_state(P, D, c.seed_base + 2)
+    x0[19:, cls == 0] = 0
+    x0_d = torch.from_numpy(x0).to(dev)
+    mult_d = torch.from_numpy(param_multipliers(P, c.rho, c.seed_base + 1)).to(dev)
+    act_d = torch.from_numpy(actions(LMAX, 8, P, c.seed_base + 3)).to(dev)
+    torch.cuda.synchronize()
+    srv = mg.Server(classes, c.dt_sub, c.substeps, fifo_plain=fifo_plain)
+    n_clients, rate = c.extra["clients"], c.extra["rate"]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    # the arrival trace: per client a Poisson stream of rate / n_clients
+    trace = []
+    for k in range(n_clients):
+        t = 0.0
+        while True:
+            t += rng.exponential(n_clients / rate)
+            if t > duration_s:
+                break
+            n = int(round(np.exp(rng.uniform(np.log(c.extra["env_lo"]), np.log(c.extra["env_hi"])))))
+            L = 1 if rng.random() < 0.5 else int(rng.integers(1, LMAX + 1))
+            off = int(rng.integers(0, P - n + 1))
+            trace.append((k, t, n, L, off))
+    per_client = [[r for r in trace if r[0] == k] for k in range(n_clients)]
+    results = []
+    lock = threading.Lock()
+    t0 = mg.Server.clock_ns() + 50_000_000
+
+    def client(reqs):
+        for _, t, n, L, off in reqs:
+            at = t0 + int(t * 1e9)
+            while True:
+                wait_ns = at - mg.Server.clock_ns()
+                if wait_ns <= 0:
+                    break
+                if wait_ns > 300_000:
+                    time.sleep((wait_ns - 200_000) * 1e-9)
+            out = np.empty((D, n), np.float32)
+            st, tk = srv.submit(n, L, x0_d.data_ptr() + 4 * off, act_d.data_ptr() + 4 * off, P,
+                                out, env_class=cls[off:off + n],
+                                mult_ptr=mult_d.data_ptr() + 4 * off, arrival_ns=at)
+            with lock:
+                results.append((st, tk, n, L))
+
+    ths = [threading.Thread(target=client, args=(r,)) for r in per_client]
+    w0 = time.perf_counter()
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    lats, env_steps = [], 0
+    for st, tk, n, L in results:
+        if st != 0:
+            continue
+        st2, lat = srv.wait(tk, 600_000_000)
+        if st2 == 0:
+            lats.append(lat)
+            env_steps += n * L
+    wall = time.perf_counter() - w0
+    stats = srv.stats()
+    srv.close()
+    lats = np.array(lats)
+    return {"mode": "fifo_plain_one_at_a_time" if fifo_plain else "continuous_batching",
+            "requests": len(trace), "completed": int(len(lats)),
+            "offered_req_per_s": len(trace) / duration_s, "trace_s": duration_s,
+            "wall_s": wall, "req_per_s": len(lats) / wall,
+            "env_control_steps_per_s": env_steps / wall,
+            "env_steps_per_s": env_steps * c.substeps / wall,
+            "p50_ms": float(np.percentile(lats, 50) * 1e3),
+            "p99_ms": float(np.percentile(lats, 99) * 1e3),
+            "p999_ms": float(np.percentile(lats, 99.9) * 1e3),
+            "max_active_envs": stats["max_active_envs"], "ticks": stats["ticks"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the environments are independent and this "
@@ -272,6 +360,11 @@ def main():
 
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, mg)
+    if not args.no_serve:
+        cb = bench_serving(torch, mg, args.serve_seconds)
+        base = bench_serving(torch, mg, args.serve_seconds, fifo_plain=True)
+        out["serving"] = {"continuous_batching": cb, "baseline_fifo_plain": base,
+                          "p99_speedup_vs_baseline": base["p99_ms"] / cb["p99_ms"]}
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline()
     print(json.dumps(out), flush=True)
 

@@ -202,6 +202,87 @@ mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, 
                           int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
                           float* dL_dtheta, float* dL_dx0);
 
+/* ---- serving loop -------------------------------------------------------------------
+ * Serves step and rollout requests of uneven env counts from many client
+ * threads on one GPU: the parallel environments of Sec. II, batched across
+ * requests.  Continuous batching: a scheduler thread admits queued requests
+ * FIFO whenever their pages (64 envs of one class each) fit under the memory
+ * cap, keeps their states on the device, and advances every admitted request
+ * by one control step per tick with one persistent launch per vehicle class
+ * replayed from a HIP graph; a request that arrives while others run joins at
+ * the next tick, and a finished one frees its pages at once.  Each env goes
+ * through exactly the arithmetic of mg_step, so a request's result does not
+ * depend on what else is in flight.
+ *
+ * mg_server_config
+ *   classes, n_classes, dt_sub, substeps, device  as in mg_config
+ *   mem_cap_bytes  page memory cap (> 0), or 0 to use mem_fraction
+ *   mem_fraction   cap as a fraction of the device memory (0 -> 0.8)
+ *   fifo_plain     1: baseline mode -- one request at a time, plain kernel
+ *                  (one launch per sub-step); same results
+ *   max_queue      bound of the admission queue (0 -> 65536)
+ * mg_request (everything the client passes stays owned by the client and
+ * must stay valid until the request completes)
+ *   n_envs, n_steps  env count (>= 1) and control steps (>= 1; 1 = a step request)
+ *   env_class        host [n_envs] class per env, or NULL (all class 0); copied at submit
+ *   x0               device [D][ld] initial states (first n_envs columns)
+ *   param_mult       device [23][ld] parameter multipliers, or NULL (nominal)
+ *   actions          device [n_steps][N_max][ld] throttles
+ *   ld               column stride of x0, param_mult and actions (>= n_envs)
+ *   out              host [D][n_envs]: the final states, written before completion
+ *   arrival_ns       arrival stamp on the mg_clock_ns() clock, or 0 (= at submit;
+ *                    a stamp later than the submission is replaced by it);
+ *                    latency is measured from it to the moment out is written */
+typedef struct mg_server mg_server;
+
+typedef struct {
+  uint32_t abi_version;
+  int32_t n_classes;
+  const mg_vehicle* classes;
+  double dt_sub;
+  int32_t substeps;
+  int32_t device;
+  int64_t mem_cap_bytes;
+  double mem_fraction;
+  int32_t fifo_plain;
+  int32_t max_queue;
+} mg_server_config;
+
+typedef struct {
+  int64_t n_envs;
+  int32_t n_steps;
+  int32_t reserved;
+  const int32_t* env_class;
+  const float* x0;
+  const float* param_mult;
+  const float* actions;
+  int64_t ld;
+  float* out;
+  uint64_t arrival_ns;
+} mg_request;
+
+typedef struct {
+  int64_t completed, rejected, ticks, env_steps, active_envs, max_active_envs, queued;
+  int64_t cap_pages, created_pages;
+} mg_server_stats;
+
+uint64_t mg_clock_ns(void);
+/* Starts the scheduler thread; page memory is taken in slabs as needed up to the cap. */
+mg_status mg_server_create(const mg_server_config* cfg, mg_server** out);
+/* Thread-safe.  MG_ERR_INVALID for a malformed request or one whose pages exceed
+ * the whole cap (counted as rejected); MG_ERR_BUSY if the queue is full. */
+mg_status mg_server_submit(mg_server* srv, const mg_request* req, uint64_t* ticket);
+/* Waits up to timeout_us (< 0: forever) for a ticket; MG_OK once its result is in
+ * out (the ticket is then consumed and *latency_s, if not NULL, receives
+ * arrival-to-completion seconds), MG_ERR_BUSY on timeout, MG_ERR_INVALID for an
+ * unknown ticket, MG_ERR_DEVICE if the server failed. */
+mg_status mg_server_wait(mg_server* srv, uint64_t ticket, int64_t timeout_us, double* latency_s);
+mg_status mg_server_get_stats(const mg_server* srv, mg_server_stats* out);
+const char* mg_server_last_error(const mg_server* srv);
+/* Stops accepting requests, finishes every request already submitted, joins
+ * the scheduler and frees everything; NULL is ignored. */
+void mg_server_destroy(mg_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

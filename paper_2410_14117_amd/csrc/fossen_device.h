@@ -11,6 +11,7 @@
 #pragma once
 
 #include "mg_internal.h"
+#include "page_pool.h"
 
 namespace mg {
 
@@ -49,6 +50,40 @@ __device__ __forceinline__ EnvConst load_env_const(const float* __restrict__ der
   P.wmb = der[kWmB * Ep + j];
   P.hz = der[kHz * Ep + j];
   return P;
+}
+
+// Per-env factorisation done once at reset: M = M_RB + M_A for diagonal I_g
+// and M_A with r_g = (0,0,z_g) couples only (u,q) and (v,p), so M^-1 is two
+// 2x2 inverses and two reciprocals; formed in FP64 from the parameters
+// prm = (m, I(3), M_A(6), D_L(6), D_Q(6), B) and rounded once.  A mass matrix
+// that is not positive definite yields NaN constants.
+__device__ __forceinline__ void derive_constants(const double (&prm)[kNumParams], double zg,
+                                                 double zb, float (&out)[kNumDerived]) {
+  const double m = prm[0];
+  const double Muu = m + prm[4], Mvv = m + prm[5], Mww = m + prm[6];
+  const double Mpp = prm[1] + m * zg * zg + prm[7];
+  const double Mqq = prm[2] + m * zg * zg + prm[8];
+  const double Mrr = prm[3] + prm[9];
+  const double Muq = m * zg, Mvp = -m * zg;
+  const double det_uq = Muu * Mqq - Muq * Muq, det_vp = Mvv * Mpp - Mvp * Mvp;
+  const bool spd = Muu > 0.0 && Mvv > 0.0 && Mww > 0.0 && Mrr > 0.0 && det_uq > 0.0 &&
+                   det_vp > 0.0;
+  double dv[kNumDerived];
+  dv[kMuu] = Muu; dv[kMvv] = Mvv; dv[kMww] = Mww; dv[kMpp] = Mpp; dv[kMqq] = Mqq;
+  dv[kMrr] = Mrr; dv[kMuq] = Muq; dv[kMvp] = Mvp;
+  dv[kIuu] = Mqq / det_uq; dv[kIqq] = Muu / det_uq; dv[kIuq] = -Muq / det_uq;
+  dv[kIvv] = Mpp / det_vp; dv[kIpp] = Mvv / det_vp; dv[kIvp] = -Mvp / det_vp;
+  dv[kIww] = 1.0 / Mww; dv[kIrr] = 1.0 / Mrr;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    dv[kDL + i] = prm[10 + i];
+    dv[kDQ + i] = prm[16 + i];
+  }
+  const double W = m * kG0, B = prm[22];
+  dv[kWmB] = W - B;
+  dv[kHz] = W * zg - B * zb;
+#pragma unroll
+  for (int i = 0; i < kNumDerived; ++i) out[i] = spd ? (float)dv[i] : __builtin_nanf("");
 }
 
 template <int N, bool LAG>

@@ -209,32 +209,10 @@ __global__ void __launch_bounds__(256) k_reset(const ResetArgs a) {
     prm[i] = (double)pf;
     a.params[i * a.Ep + j] = pf;
   }
-  const double m = prm[0], zg = nom.zg, zb = nom.zb;
-  const double Muu = m + prm[4], Mvv = m + prm[5], Mww = m + prm[6];
-  const double Mpp = prm[1] + m * zg * zg + prm[7];
-  const double Mqq = prm[2] + m * zg * zg + prm[8];
-  const double Mrr = prm[3] + prm[9];
-  const double Muq = m * zg, Mvp = -m * zg;
-  const double det_uq = Muu * Mqq - Muq * Muq, det_vp = Mvv * Mpp - Mvp * Mvp;
-  const bool spd = Muu > 0.0 && Mvv > 0.0 && Mww > 0.0 && Mrr > 0.0 && det_uq > 0.0 &&
-                   det_vp > 0.0;
-  double dv[kNumDerived];
-  dv[kMuu] = Muu; dv[kMvv] = Mvv; dv[kMww] = Mww; dv[kMpp] = Mpp; dv[kMqq] = Mqq;
-  dv[kMrr] = Mrr; dv[kMuq] = Muq; dv[kMvp] = Mvp;
-  dv[kIuu] = Mqq / det_uq; dv[kIqq] = Muu / det_uq; dv[kIuq] = -Muq / det_uq;
-  dv[kIvv] = Mpp / det_vp; dv[kIpp] = Mvv / det_vp; dv[kIvp] = -Mvp / det_vp;
-  dv[kIww] = 1.0 / Mww; dv[kIrr] = 1.0 / Mrr;
+  float dvf[kNumDerived];
+  derive_constants(prm, nom.zg, nom.zb, dvf);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    dv[kDL + i] = prm[10 + i];
-    dv[kDQ + i] = prm[16 + i];
-  }
-  const double W = m * kG0, B = prm[22];
-  dv[kWmB] = W - B;
-  dv[kHz] = W * zg - B * zb;
-#pragma unroll
-  for (int i = 0; i < kNumDerived; ++i)
-    a.derived[i * a.Ep + j] = spd ? (float)dv[i] : __builtin_nanf("");
+  for (int i = 0; i < kNumDerived; ++i) a.derived[i * a.Ep + j] = dvf[i];
 
   if (a.write_state) {
     const int Dc = 13 + (nom.lag ? nom.n_thr : 0);

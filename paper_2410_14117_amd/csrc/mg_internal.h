@@ -105,6 +105,44 @@ struct AdjArgs {
   float zb;                    // class z_b (for dL/dB through h_z)
 };
 
+// ---- serving loop (kernels_serve.hip) -------------------------------------
+// A page is a block of (Dmax + kNumDerived) rows x 64 lanes of floats: the
+// state rows first, then the per-env derived constants; its column map gives,
+// per lane, the env's column in the request's input arrays (-1 = empty lane).
+struct ServeInitItem {         // one newly admitted page
+  float* block;
+  const int32_t* cols_src;     // staged column map of the page (64 entries)
+  int32_t* cols;               // the page's own column map (written here)
+  const float* x0;             // request [D][ld]
+  const float* mult;           // request [23][ld] or NULL
+  int64_t ld;
+  int32_t cls;
+  int32_t pad_;
+};
+struct ServeTickItem {         // one active page, one control step
+  float* block;
+  const int32_t* cols;
+  const float* actions;        // request [L][n_max][ld]
+  int64_t ld;
+  int32_t step;
+  int32_t pad_;
+};
+struct ServeGatherItem {       // one page of a finished request
+  const float* block;
+  const int32_t* cols;
+  float* out;                  // device staging [Dmax][n] of the request
+  int64_t n;
+};
+hipError_t launch_serve_init(const ServeInitItem* items, int32_t n_items,
+                             const ClassNominal* nominal, int32_t Dmax, hipStream_t s);
+// grid is fixed (persistent) so the launch can live in a replayed graph; the
+// number of items is read from *count on the device
+hipError_t launch_serve_tick(const ClassConst& cc, const ServeTickItem* items,
+                             const int32_t* count, int32_t Dmax, int32_t n_max, int32_t substeps,
+                             float dt, int32_t grid, hipStream_t s);
+hipError_t launch_serve_gather(const ServeGatherItem* items, int32_t n_items, int32_t Dmax,
+                               hipStream_t s);
+
 // launchers (kernels_adjoint.hip)
 hipError_t launch_adjoint(bool backward, const ClassConst& cc, const AdjArgs& a, hipStream_t s);
 

@@ -1,0 +1,636 @@
+// server.hip -- continuous-batching serving loop for step/rollout requests of
+// uneven env counts (the many-parallel-environments setting of Sec. II, served
+// to many clients at once).
+//
+// Requests enter a FIFO admission queue.  A scheduler thread runs ticks: it
+// admits queued requests while their pages fit under the memory cap, writes
+// their envs into 64-env single-class pages (state + per-env factorisation,
+// k_serve_init), advances every active page by one control step with one
+// persistent launch per vehicle class replayed from a HIP graph, and retires
+// finished requests (k_serve_gather, copy to the client's host buffer, pages
+// freed).  States stay on the device for the whole life of a request;
+// requests that arrive while others run join at the next tick.
+#include "mg.h"
+#include "mg_internal.h"
+#include "page_pool.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+using namespace mg;
+
+namespace {
+
+thread_local std::string g_server_create_error;
+
+uint64_t clock_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  int64_t n = 0;
+  int32_t L = 0, step = 0;
+  std::vector<int32_t> cls;          // host copy of the env classes
+  std::vector<int64_t> per_class;    // env count per class
+  const float* x0 = nullptr;
+  const float* mult = nullptr;
+  const float* actions = nullptr;
+  int64_t ld = 0;
+  float* out = nullptr;
+  uint64_t arrival = 0;
+  std::vector<int64_t> pages;
+  std::vector<int32_t> page_cls;
+  std::vector<int32_t> cols;         // [pages][64]
+};
+
+struct Record {
+  uint64_t arrival = 0, done = 0;
+  mg_status status = MG_OK;
+  bool finished = false;
+};
+
+template <class T>
+struct Mirror {   // pinned host buffer + device buffer of the same capacity
+  T* h = nullptr;
+  T* d = nullptr;
+  size_t cap = 0;
+  bool grow(size_t need) {
+    if (need <= cap) return true;
+    size_t c = std::max<size_t>(need, cap * 2 + 64);
+    release();
+    if (hipHostMalloc((void**)&h, c * sizeof(T), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&d, c * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      release();
+      return false;
+    }
+    cap = c;
+    return true;
+  }
+  void release() {
+    if (h) (void)hipHostFree(h);
+    if (d) (void)hipFree(d);
+    h = nullptr;
+    d = nullptr;
+    cap = 0;
+  }
+};
+
+}  // namespace
+
+struct mg_server {
+  int device = 0;
+  int32_t D = 13, n_max = 1, substeps = 1, n_classes = 1;
+  double dt = 0.005;
+  bool fifo_plain = false;
+  int64_t max_queue = 65536;
+  std::vector<ClassConst> cc;
+  std::vector<ClassNominal> nominal;
+  ClassNominal* nominal_dev = nullptr;
+  hipStream_t stream = nullptr;
+
+  // pages
+  int64_t page_floats = 0, slab_pages = 1024;
+  std::unique_ptr<PagePool> pool;
+  std::vector<float*> slab_blocks;
+  std::vector<int32_t*> slab_cols;
+  float* page_block(int64_t p) const {
+    return slab_blocks[p / slab_pages] + (p % slab_pages) * page_floats;
+  }
+  int32_t* page_cols(int64_t p) const {
+    return slab_cols[p / slab_pages] + (p % slab_pages) * kPageEnvs;
+  }
+
+  // per-tick lists
+  Mirror<ServeInitItem> init;
+  Mirror<int32_t> cols_stage;
+  Mirror<ServeTickItem> tick;      // n_classes regions of tick_cap entries
+  Mirror<int32_t> counts;
+  Mirror<ServeGatherItem> gather;
+  Mirror<float> out;
+  size_t tick_cap = 0;
+  hipGraphExec_t graph = nullptr;
+  int32_t grid = 1024;
+
+  // queue, records, thread
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done;
+  std::deque<Request*> queue;
+  std::vector<Request*> active;    // scheduler thread only
+  std::unordered_map<uint64_t, Record> records;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  bool broken = false;
+  std::string err;
+  std::thread thr;
+
+  // statistics
+  std::atomic<int64_t> completed{0}, rejected{0}, ticks{0}, env_steps{0}, active_envs{0},
+      max_active_envs{0}, queued{0};
+};
+
+namespace {
+
+bool fail_server(mg_server* S, const std::string& msg) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->broken = true;
+  S->err = msg;
+  return false;
+}
+
+#define SV_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return fail_server(S, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+ClassConst class_const(const mg_vehicle& v, double dt) {
+  ClassConst c;
+  std::memset(&c, 0, sizeof(c));
+  for (int i = 0; i < v.n_thr; ++i) {
+    const double* r = v.thr_pos[i];
+    const double* d = v.thr_dir[i];
+    const double col[6] = {d[0], d[1], d[2], r[1] * d[2] - r[2] * d[1],
+                           r[2] * d[0] - r[0] * d[2], r[0] * d[1] - r[1] * d[0]};
+    for (int k = 0; k < 6; ++k) c.B[k][i] = (float)col[k];
+  }
+  c.f_max = (float)v.f_max;
+  c.inv_tau = v.thr_tau > 0.0 ? (float)(1.0 / v.thr_tau) : 0.0f;
+  const double z = v.thr_tau > 0.0 ? dt / v.thr_tau : 0.0;
+  c.sigma2 = (float)(1.0 - z / 2);
+  c.sigma3 = (float)(1.0 - z / 2 + z * z / 4);
+  c.sigma4 = (float)(1.0 - z + z * z / 2 - z * z * z / 4);
+  c.rho = (float)(1.0 - z + z * z / 2 - z * z * z / 6 + z * z * z * z / 24);
+  c.n_thr = v.n_thr;
+  c.thr_map = v.thr_map;
+  c.lag = v.thr_tau > 0.0 ? 1 : 0;
+  return c;
+}
+
+ClassNominal class_nominal(const mg_vehicle& v) {
+  ClassNominal n;
+  std::memset(&n, 0, sizeof(n));
+  n.p[0] = v.mass;
+  for (int i = 0; i < 3; ++i) n.p[1 + i] = v.inertia[i];
+  for (int i = 0; i < 6; ++i) {
+    n.p[4 + i] = v.added_mass[i];
+    n.p[10 + i] = v.d_lin[i];
+    n.p[16 + i] = v.d_quad[i];
+  }
+  n.p[22] = v.buoyancy;
+  n.zg = v.r_g[2];
+  n.zb = v.r_b[2];
+  n.n_thr = v.n_thr;
+  n.lag = v.thr_tau > 0.0 ? 1 : 0;
+  return n;
+}
+
+// (Re)captures the tick graph: one persistent launch per class (fused: one
+// control step of `substeps` sub-steps; FIFO baseline: `substeps` plain
+// launches of one sub-step), reading its items and count from fixed buffers.
+bool capture_tick_graph(mg_server* S) {
+  if (S->graph) {
+    (void)hipGraphExecDestroy(S->graph);
+    S->graph = nullptr;
+  }
+  hipStream_t cap;
+  SV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  const int reps = S->fifo_plain ? S->substeps : 1;
+  const int sub = S->fifo_plain ? 1 : S->substeps;
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    for (int c = 0; c < S->n_classes && e == hipSuccess; ++c)
+      e = launch_serve_tick(S->cc[c], S->tick.d + (size_t)c * S->tick_cap, S->counts.d + c, S->D,
+                            S->n_max, sub, (float)S->dt, S->grid, cap);
+  hipError_t e2 = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail_server(S, "tick graph capture failed");
+  }
+  hipError_t e3 = hipGraphInstantiate(&S->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e3 != hipSuccess) return fail_server(S, "tick graph instantiate failed");
+  return true;
+}
+
+void finish(mg_server* S, Request* r, mg_status st) {
+  const uint64_t t = clock_ns();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    Record& rec = S->records[r->ticket];
+    rec.done = t;
+    rec.status = st;
+    rec.finished = true;
+  }
+  S->cv_done.notify_all();
+  if (st == MG_OK) S->completed.fetch_add(1);
+  delete r;
+}
+
+// One tick: initialise admitted pages, advance every active page one control
+// step, retire finished requests.  Returns false on a device error.
+bool tick(mg_server* S, std::vector<Request*>& admitted) {
+  // 1. newly admitted pages
+  size_t n_init = 0;
+  for (Request* r : admitted) n_init += r->pages.size();
+  if (n_init) {
+    if (!S->init.grow(n_init) || !S->cols_stage.grow(n_init * kPageEnvs))
+      return fail_server(S, "host/device staging allocation failed");
+    size_t k = 0;
+    for (Request* r : admitted) {
+      for (size_t p = 0; p < r->pages.size(); ++p, ++k) {
+        ServeInitItem& it = S->init.h[k];
+        std::memcpy(S->cols_stage.h + k * kPageEnvs, r->cols.data() + p * kPageEnvs,
+                    kPageEnvs * sizeof(int32_t));
+        it.block = S->page_block(r->pages[p]);
+        it.cols_src = S->cols_stage.d + k * kPageEnvs;
+        it.cols = S->page_cols(r->pages[p]);
+        it.x0 = r->x0;
+        it.mult = r->mult;
+        it.ld = r->ld;
+        it.cls = r->page_cls[p];
+        it.pad_ = 0;
+      }
+    }
+    SV_HIP(hipMemcpyAsync(S->cols_stage.d, S->cols_stage.h, n_init * kPageEnvs * sizeof(int32_t),
+                          hipMemcpyHostToDevice, S->stream));
+    SV_HIP(hipMemcpyAsync(S->init.d, S->init.h, n_init * sizeof(ServeInitItem),
+                          hipMemcpyHostToDevice, S->stream));
+    SV_HIP(launch_serve_init(S->init.d, (int32_t)n_init, S->nominal_dev, S->D, S->stream));
+    for (Request* r : admitted) S->active.push_back(r);
+    admitted.clear();
+  }
+
+  // 2. the tick itself
+  std::vector<size_t> per(S->n_classes, 0);
+  for (Request* r : S->active)
+    for (int32_t c : r->page_cls) ++per[c];
+  size_t need = 0;
+  for (size_t v : per) need = std::max(need, v);
+  if (need > S->tick_cap) {
+    SV_HIP(hipStreamSynchronize(S->stream));
+    const size_t cap = std::max<size_t>(need, 2 * S->tick_cap + 256);
+    if (!S->tick.grow(cap * S->n_classes)) return fail_server(S, "tick list allocation failed");
+    S->tick_cap = cap;
+    if (!capture_tick_graph(S)) return false;
+  }
+  std::vector<size_t> fill(S->n_classes, 0);
+  int64_t envs = 0;
+  for (Request* r : S->active) {
+    for (size_t p = 0; p < r->pages.size(); ++p) {
+      const int32_t c = r->page_cls[p];
+      ServeTickItem& it = S->tick.h[(size_t)c * S->tick_cap + fill[c]++];
+      it.block = S->page_block(r->pages[p]);
+      it.cols = S->page_cols(r->pages[p]);
+      it.actions = r->actions;
+      it.ld = r->ld;
+      it.step = r->step;
+      it.pad_ = 0;
+    }
+    envs += r->n;
+  }
+  for (int c = 0; c < S->n_classes; ++c) S->counts.h[c] = (int32_t)fill[c];
+  for (int c = 0; c < S->n_classes; ++c)
+    if (fill[c])
+      SV_HIP(hipMemcpyAsync(S->tick.d + (size_t)c * S->tick_cap, S->tick.h + (size_t)c * S->tick_cap,
+                            fill[c] * sizeof(ServeTickItem), hipMemcpyHostToDevice, S->stream));
+  SV_HIP(hipMemcpyAsync(S->counts.d, S->counts.h, S->n_classes * sizeof(int32_t),
+                        hipMemcpyHostToDevice, S->stream));
+  SV_HIP(hipGraphLaunch(S->graph, S->stream));
+  S->active_envs.store(envs);
+  if (envs > S->max_active_envs.load()) S->max_active_envs.store(envs);
+  S->env_steps.fetch_add(envs);
+  S->ticks.fetch_add(1);
+
+  // 3. retire the requests whose last control step this was
+  std::vector<Request*> done, keep;
+  for (Request* r : S->active) {
+    ++r->step;
+    (r->step >= r->L ? done : keep).push_back(r);
+  }
+  S->active.swap(keep);
+  size_t n_gat = 0, n_out = 0;
+  for (Request* r : done) {
+    n_gat += r->pages.size();
+    n_out += (size_t)r->n * S->D;
+  }
+  if (!done.empty()) {
+    if (!S->gather.grow(n_gat) || !S->out.grow(n_out))
+      return fail_server(S, "gather staging allocation failed");
+    size_t k = 0, o = 0;
+    for (Request* r : done) {
+      for (size_t p = 0; p < r->pages.size(); ++p, ++k) {
+        ServeGatherItem& it = S->gather.h[k];
+        it.block = S->page_block(r->pages[p]);
+        it.cols = S->page_cols(r->pages[p]);
+        it.out = S->out.d + o;
+        it.n = r->n;
+      }
+      o += (size_t)r->n * S->D;
+    }
+    SV_HIP(hipMemcpyAsync(S->gather.d, S->gather.h, n_gat * sizeof(ServeGatherItem),
+                          hipMemcpyHostToDevice, S->stream));
+    SV_HIP(launch_serve_gather(S->gather.d, (int32_t)n_gat, S->D, S->stream));
+    SV_HIP(hipMemcpyAsync(S->out.h, S->out.d, n_out * sizeof(float), hipMemcpyDeviceToHost,
+                          S->stream));
+  }
+  SV_HIP(hipStreamSynchronize(S->stream));
+  size_t o = 0;
+  for (Request* r : done) {
+    std::memcpy(r->out, S->out.h + o, (size_t)r->n * S->D * sizeof(float));
+    o += (size_t)r->n * S->D;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->pool->release(r->pages);
+    }
+    finish(S, r, MG_OK);
+  }
+  return true;
+}
+
+void scheduler(mg_server* S) {
+  (void)hipSetDevice(S->device);
+  std::vector<Request*> admitted;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (S->active.empty()) {
+        S->cv_sched.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+        if (S->queue.empty() && S->stop) break;
+      }
+      // FIFO admission while the pages fit under the cap (FIFO baseline: one at a time)
+      while (!S->queue.empty() && !S->broken) {
+        if (S->fifo_plain && (!S->active.empty() || !admitted.empty())) break;
+        Request* r = S->queue.front();
+        const int64_t need = PagePool::pages_for(r->per_class);
+        if (!S->pool->fits(need)) break;
+        std::vector<int64_t> pages;
+        if (!S->pool->allocate(need, pages)) {
+          // the cap allows it but device memory could not be obtained: with nothing
+          // in flight to free pages, this request cannot make progress
+          if (!S->active.empty() || !admitted.empty()) break;
+          S->queue.pop_front();
+          S->queued.fetch_sub(1);
+          lk.unlock();
+          finish(S, r, MG_ERR_OOM);
+          lk.lock();
+          continue;
+        }
+        S->queue.pop_front();
+        S->queued.fetch_sub(1);
+        // pages per class in class order; lanes take the class's envs in request order
+        r->pages = pages;
+        r->page_cls.clear();
+        r->cols.assign(pages.size() * kPageEnvs, -1);
+        size_t p = 0;
+        for (int c = 0; c < S->n_classes; ++c) {
+          int lane = 0;
+          if (r->per_class[c] == 0) continue;
+          r->page_cls.push_back(c);
+          for (int64_t e = 0; e < r->n; ++e) {
+            if (r->cls[e] != c) continue;
+            if (lane == kPageEnvs) {
+              lane = 0;
+              ++p;
+              r->page_cls.push_back(c);
+            }
+            r->cols[p * kPageEnvs + lane++] = (int32_t)e;
+          }
+          ++p;
+        }
+        admitted.push_back(r);
+      }
+      if (S->broken) {
+        lk.unlock();
+        break;
+      }
+    }
+    if (admitted.empty() && S->active.empty()) continue;
+    if (!tick(S, admitted)) break;
+  }
+  // drain: anything left fails (device error or shutdown)
+  const mg_status st = S->broken ? MG_ERR_DEVICE : MG_ERR_BUSY;
+  for (Request* r : admitted) finish(S, r, st);
+  for (Request* r : S->active) finish(S, r, st);
+  S->active.clear();
+  std::deque<Request*> q;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    q.swap(S->queue);
+  }
+  for (Request* r : q) finish(S, r, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t mg_clock_ns(void) { return clock_ns(); }
+
+const char* mg_server_last_error(const mg_server* S) {
+  return S ? S->err.c_str() : g_server_create_error.c_str();
+}
+
+mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
+  auto bad = [](mg_status st, const char* m) {
+    g_server_create_error = m;
+    return st;
+  };
+  if (!out) return bad(MG_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!cfg || cfg->abi_version != MG_ABI_VERSION) return bad(MG_ERR_INVALID, "bad config / ABI version");
+  if (cfg->n_classes < 1 || cfg->n_classes > MG_MAX_CLASSES || !cfg->classes)
+    return bad(MG_ERR_INVALID, "n_classes outside 1..16 or classes NULL");
+  if (!(cfg->dt_sub > 0.0) || cfg->substeps < 1) return bad(MG_ERR_INVALID, "dt_sub / substeps");
+  for (int k = 0; k < cfg->n_classes; ++k) {
+    const mg_vehicle& v = cfg->classes[k];
+    if (v.n_thr < 1 || v.n_thr > MG_MAX_THRUSTERS || (v.thr_map != 0 && v.thr_map != 1) ||
+        v.thr_tau < 0.0)
+      return bad(MG_ERR_INVALID, "invalid vehicle class");
+    if (v.r_g[0] != 0.0 || v.r_g[1] != 0.0 || v.r_b[0] != 0.0 || v.r_b[1] != 0.0)
+      return bad(MG_ERR_UNSUPPORTED, "the GPU path needs r_g and r_b on the body z axis");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return bad(MG_ERR_DEVICE, "no HIP device");
+  }
+  if (cfg->device < 0 || cfg->device >= ndev) return bad(MG_ERR_INVALID, "bad device ordinal");
+  if (hipSetDevice(cfg->device) != hipSuccess) return bad(MG_ERR_DEVICE, "hipSetDevice failed");
+
+  auto S = std::make_unique<mg_server>();
+  S->device = cfg->device;
+  S->n_classes = cfg->n_classes;
+  S->substeps = cfg->substeps;
+  S->dt = cfg->dt_sub;
+  S->fifo_plain = cfg->fifo_plain != 0;
+  S->max_queue = cfg->max_queue > 0 ? cfg->max_queue : 65536;
+  for (int k = 0; k < cfg->n_classes; ++k) {
+    const mg_vehicle& v = cfg->classes[k];
+    S->cc.push_back(class_const(v, cfg->dt_sub));
+    S->nominal.push_back(class_nominal(v));
+    S->n_max = std::max(S->n_max, v.n_thr);
+    if (v.thr_tau > 0.0) S->D = std::max(S->D, 13 + v.n_thr);
+  }
+  S->page_floats = (int64_t)(S->D + kNumDerived) * kPageEnvs;
+  const int64_t page_bytes = S->page_floats * 4 + kPageEnvs * 4;
+  int64_t cap_bytes = cfg->mem_cap_bytes;
+  if (cap_bytes <= 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return bad(MG_ERR_DEVICE, "hipMemGetInfo failed");
+    const double frac = cfg->mem_fraction > 0.0 ? cfg->mem_fraction : 0.8;
+    cap_bytes = (int64_t)(frac * (double)total_b);
+  }
+  const int64_t cap_pages = cap_bytes / page_bytes;
+  if (cap_pages < 1) return bad(MG_ERR_INVALID, "memory cap below one page");
+  S->slab_pages = std::min<int64_t>(1024, cap_pages);
+  mg_server* raw = S.get();
+  S->pool = std::make_unique<PagePool>(cap_pages, S->slab_pages, [raw](int64_t first, int64_t n) {
+    (void)first;
+    float* b = nullptr;
+    int32_t* c = nullptr;
+    if (hipMalloc((void**)&b, (size_t)n * raw->page_floats * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&c, (size_t)n * kPageEnvs * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (b) (void)hipFree(b);
+      return false;
+    }
+    raw->slab_blocks.push_back(b);
+    raw->slab_cols.push_back(c);
+    return true;
+  });
+  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc(&S->nominal_dev, sizeof(ClassNominal) * S->n_classes) != hipSuccess ||
+      hipMemcpy(S->nominal_dev, S->nominal.data(), sizeof(ClassNominal) * S->n_classes,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      !S->counts.grow(MG_MAX_CLASSES)) {
+    (void)hipGetLastError();
+    mg_server_destroy(S.release());
+    return bad(MG_ERR_DEVICE, "server initialisation failed");
+  }
+  S->tick_cap = 256;
+  if (!S->tick.grow(S->tick_cap * S->n_classes) || !capture_tick_graph(S.get())) {
+    mg_server_destroy(S.release());
+    return bad(MG_ERR_DEVICE, "tick graph initialisation failed");
+  }
+  S->thr = std::thread(scheduler, S.get());
+  *out = S.release();
+  return MG_OK;
+}
+
+mg_status mg_server_submit(mg_server* S, const mg_request* req, uint64_t* ticket) {
+  if (!S || !req || !ticket) return MG_ERR_INVALID;
+  if (req->n_envs < 1 || req->n_steps < 1 || !req->x0 || !req->actions || !req->out ||
+      req->ld < req->n_envs)
+    return MG_ERR_INVALID;
+  auto r = std::make_unique<Request>();
+  r->n = req->n_envs;
+  r->L = req->n_steps;
+  r->cls.assign(req->n_envs, 0);
+  if (req->env_class) std::memcpy(r->cls.data(), req->env_class, sizeof(int32_t) * req->n_envs);
+  r->per_class.assign(S->n_classes, 0);
+  for (int32_t c : r->cls) {
+    if (c < 0 || c >= S->n_classes) return MG_ERR_INVALID;
+    ++r->per_class[c];
+  }
+  r->x0 = req->x0;
+  r->mult = req->param_mult;
+  r->actions = req->actions;
+  r->ld = req->ld;
+  r->out = req->out;
+  // an arrival stamp in the future (a client submitting early) counts from submission
+  const uint64_t now = clock_ns();
+  r->arrival = (req->arrival_ns && req->arrival_ns < now) ? req->arrival_ns : now;
+  const int64_t need = PagePool::pages_for(r->per_class);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->broken) return MG_ERR_DEVICE;
+    if (S->stop) return MG_ERR_BUSY;
+    if (!S->pool->ever_fits(need)) {
+      S->rejected.fetch_add(1);
+      return MG_ERR_INVALID;
+    }
+    if ((int64_t)S->queue.size() >= S->max_queue) return MG_ERR_BUSY;
+    r->ticket = S->next_ticket++;
+    Record rec;
+    rec.arrival = r->arrival;
+    S->records[r->ticket] = rec;
+    *ticket = r->ticket;
+    S->queue.push_back(r.release());
+    S->queued.fetch_add(1);
+  }
+  S->cv_sched.notify_one();
+  return MG_OK;
+}
+
+mg_status mg_server_wait(mg_server* S, uint64_t ticket, int64_t timeout_us, double* latency_s) {
+  if (!S) return MG_ERR_INVALID;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->records.find(ticket);
+  if (it == S->records.end()) return MG_ERR_INVALID;
+  auto ready = [&] { return S->records[ticket].finished; };
+  if (timeout_us < 0)
+    S->cv_done.wait(lk, ready);
+  else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+    return MG_ERR_BUSY;
+  Record rec = S->records[ticket];
+  S->records.erase(ticket);
+  if (latency_s) *latency_s = (double)(rec.done - rec.arrival) * 1e-9;
+  return rec.status;
+}
+
+mg_status mg_server_get_stats(const mg_server* S, mg_server_stats* out) {
+  if (!S || !out) return MG_ERR_INVALID;
+  out->completed = S->completed.load();
+  out->rejected = S->rejected.load();
+  out->ticks = S->ticks.load();
+  out->env_steps = S->env_steps.load();
+  out->active_envs = S->active_envs.load();
+  out->max_active_envs = S->max_active_envs.load();
+  out->queued = S->queued.load();
+  out->cap_pages = S->pool ? S->pool->cap_pages() : 0;
+  out->created_pages = S->pool ? S->pool->created_pages() : 0;
+  return S->broken ? MG_ERR_DEVICE : MG_OK;
+}
+
+void mg_server_destroy(mg_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_sched.notify_all();
+  if (S->thr.joinable()) S->thr.join();
+  (void)hipSetDevice(S->device);
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  if (S->graph) (void)hipGraphExecDestroy(S->graph);
+  S->init.release();
+  S->cols_stage.release();
+  S->tick.release();
+  S->counts.release();
+  S->gather.release();
+  S->out.release();
+  for (float* b : S->slab_blocks) (void)hipFree(b);
+  for (int32_t* c : S->slab_cols) (void)hipFree(c);
+  if (S->nominal_dev) (void)hipFree(S->nominal_dev);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  (void)hipGetLastError();
+  delete S;
+}
+
+}  // extern "C"

@@ -48,6 +48,31 @@ class MgConfig(ctypes.Structure):
     ]
 
 
+class MgServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32), ("n_classes", ctypes.c_int32),
+        ("classes", ctypes.POINTER(MgVehicle)), ("dt_sub", ctypes.c_double),
+        ("substeps", ctypes.c_int32), ("device", ctypes.c_int32),
+        ("mem_cap_bytes", ctypes.c_int64), ("mem_fraction", ctypes.c_double),
+        ("fifo_plain", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+    ]
+
+
+class MgRequest(ctypes.Structure):
+    _fields_ = [
+        ("n_envs", ctypes.c_int64), ("n_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("env_class", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("param_mult", ctypes.c_void_p),
+        ("actions", ctypes.c_void_p), ("ld", ctypes.c_int64), ("out", ctypes.c_void_p),
+        ("arrival_ns", ctypes.c_uint64),
+    ]
+
+
+class MgServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("completed", "rejected", "ticks", "env_steps", "active_envs", "max_active_envs",
+                 "queued", "cap_pages", "created_pages")]
+
+
 _vp = ctypes.c_void_p
 _SIGS = {
     "mg_abi_version": (ctypes.c_uint32, []),
@@ -68,6 +93,15 @@ _SIGS = {
     "mg_get_state": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
     "mg_get_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
     "mg_synchronize": (ctypes.c_int32, [_vp]),
+    "mg_clock_ns": (ctypes.c_uint64, []),
+    "mg_server_create": (ctypes.c_int32, [ctypes.POINTER(MgServerConfig), ctypes.POINTER(_vp)]),
+    "mg_server_submit": (ctypes.c_int32, [_vp, ctypes.POINTER(MgRequest),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "mg_server_wait": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "mg_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(MgServerStats)]),
+    "mg_server_last_error": (ctypes.c_char_p, [_vp]),
+    "mg_server_destroy": (None, [_vp]),
     "mg_adj_forward": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
     "mg_adj_backward": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                          _vp, _vp]),
@@ -305,3 +339,100 @@ class Sim:
         self._check(lib().mg_adj_backward(self._h, ck, a, T, K, g, gact.data_ptr(), gth.data_ptr(),
                                           None if gx0 is None else gx0.data_ptr()))
         return gact, gth, gx0
+
+
+def page_bytes(state_dim):
+    """Device bytes of one 64-env serving page (state + derived constants + column map)."""
+    return (state_dim + 30) * 64 * 4 + 64 * 4
+
+
+class Server:
+    """Continuous-batching serving loop on one GPU (wraps an ``mg_server``)."""
+
+    def __init__(self, classes, dt_sub, substeps, device=0, mem_cap_bytes=0, mem_fraction=0.0,
+                 fifo_plain=False, max_queue=0):
+        import threading
+        L = lib()
+        if isinstance(classes, dict):
+            classes = [classes]
+        self._classes = (MgVehicle * len(classes))(*[vehicle_struct(c) for c in classes])
+        cfg = MgServerConfig()
+        cfg.abi_version = MG_ABI_VERSION
+        cfg.n_classes = len(classes)
+        cfg.classes = self._classes
+        cfg.dt_sub = float(dt_sub)
+        cfg.substeps = int(substeps)
+        cfg.device = int(device)
+        cfg.mem_cap_bytes = int(mem_cap_bytes)
+        cfg.mem_fraction = float(mem_fraction)
+        cfg.fifo_plain = 1 if fifo_plain else 0
+        cfg.max_queue = int(max_queue)
+        h = _vp()
+        st = L.mg_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != MG_OK:
+            raise MgError(st, L.mg_server_last_error(None).decode())
+        self._h = h
+        self.state_dim = 13 + max([len(c["thr_pos"]) for c in classes if c["thr_tau"] > 0] or [0])
+        self.action_dim = max(len(c["thr_pos"]) for c in classes)
+        self._keep = {}
+        self._lock = threading.Lock()
+
+    @staticmethod
+    def clock_ns():
+        return lib().mg_clock_ns()
+
+    def submit(self, n_envs, n_steps, x0_ptr, actions_ptr, ld, out, env_class=None,
+               mult_ptr=None, arrival_ns=0):
+        """Device pointers x0 [D][ld], actions [n_steps][N_max][ld], mult [23][ld] (optional);
+        out: host float32 array [D][n_envs] that receives the final states.  Returns
+        (status, ticket)."""
+        if out.dtype != np.float32 or out.shape != (self.state_dim, n_envs) or \
+                not out.flags["C_CONTIGUOUS"]:
+            raise ValueError("out must be a contiguous float32 [D][n_envs] host array")
+        ec = None
+        if env_class is not None:
+            ec = np.ascontiguousarray(np.asarray(env_class, dtype=np.int32))
+            if ec.shape != (n_envs,):
+                raise ValueError("env_class must have shape [n_envs]")
+        r = MgRequest()
+        r.n_envs = int(n_envs)
+        r.n_steps = int(n_steps)
+        r.env_class = ec.ctypes.data if ec is not None else None
+        r.x0 = int(x0_ptr)
+        r.param_mult = int(mult_ptr) if mult_ptr else None
+        r.actions = int(actions_ptr)
+        r.ld = int(ld)
+        r.out = out.ctypes.data
+        r.arrival_ns = int(arrival_ns)
+        t = ctypes.c_uint64()
+        st = lib().mg_server_submit(self._h, ctypes.byref(r), ctypes.byref(t))
+        if st == MG_OK:
+            with self._lock:
+                self._keep[t.value] = out
+        return st, t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        """Returns (status, latency_s)."""
+        lat = ctypes.c_double(0.0)
+        st = lib().mg_server_wait(self._h, ctypes.c_uint64(ticket), int(timeout_us),
+                                  ctypes.byref(lat))
+        if st != MG_ERR_BUSY:
+            with self._lock:
+                self._keep.pop(ticket, None)
+        return st, lat.value
+
+    def stats(self):
+        s = MgServerStats()
+        lib().mg_server_get_stats(self._h, ctypes.byref(s))
+        return {n: getattr(s, n) for n, _ in MgServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -61,7 +61,7 @@ def _gpu_grads(mgmod, v, x0, act, mult, pref, qref, S, dt, K, classes=None, cls=
     loss = _track_loss_torch(traj, dev(pref), dev(qref))
     loss.backward()
     torch.cuda.synchronize()
-    out = (float(loss), host(a_t.grad), host(hydro.grad), host(x0_t.grad), host(traj))
+    out = (float(loss.detach()), host(a_t.grad), host(hydro.grad), host(x0_t.grad), host(traj))
     sim.close()
     return out
 

@@ -1,0 +1,202 @@
+"""GPU tests of the continuous-batching serving loop (mg_server_*).
+
+A request's final states must be the same (bitwise) alone, in a mix of
+concurrently served requests, in the FIFO baseline mode and through mg_step,
+and within the trajectory tolerance of the FP64 oracle.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from workloads import (BLUEROV2, BLUEROV2_HEAVY, vehicle_variant, initial_state, actions,
+                       param_multipliers, env_classes)
+from tests.gpu_util import dev, host, rel_err, say, TOL_TRAJ
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CLASSES = [vehicle_variant(BLUEROV2, thr_map=1, thr_tau=0.05),
+           vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)]
+DT, S, D, NMAX = 0.005, 4, 21, 8
+POOL = 40000     # columns of the shared device input pools
+LMAX = 64
+
+
+@pytest.fixture(scope="module")
+def mgmod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_14117_amd import mg
+    mg.lib()
+    return mg
+
+
+@pytest.fixture(scope="module")
+def pools(mgmod):
+    cls = env_classes(POOL, "bernoulli", 401)
+    x0 = initial_state(POOL, D, 402)
+    x0[19:, cls == 0] = 0
+    mult = param_multipliers(POOL, 0.2, 403)
+    act = actions(LMAX, NMAX, POOL, 404)
+    return {"cls": cls, "x0": x0, "mult": mult, "act": act,
+            "x0_d": dev(x0), "mult_d": dev(mult), "act_d": dev(act)}
+
+
+def _req(pools, off, n, L):
+    """Pointers into the pools: columns [off, off + n), row stride POOL."""
+    return dict(n_envs=n, n_steps=L, x0_ptr=pools["x0_d"].data_ptr() + 4 * off,
+                actions_ptr=pools["act_d"].data_ptr() + 4 * off, ld=POOL,
+                env_class=pools["cls"][off:off + n], mult_ptr=pools["mult_d"].data_ptr() + 4 * off)
+
+
+def _serve(srv, pools, reqs):
+    outs, tickets = [], []
+    for off, n, L in reqs:
+        out = np.zeros((D, n), np.float32)
+        st, t = srv.submit(out=out, **_req(pools, off, n, L))
+        assert st == 0
+        outs.append(out)
+        tickets.append(t)
+    lat = []
+    for t in tickets:
+        st, l = srv.wait(t, timeout_us=60_000_000)
+        assert st == 0
+        lat.append(l)
+    return outs, lat
+
+
+R = (1234, 1000, 20)     # the request that is checked alone and in the mix
+
+
+def test_alone_equals_mix_equals_step_and_oracle(mgmod, pools, oracle):
+    say("serve alone")
+    srv = mgmod.Server(CLASSES, DT, S)
+    (alone,), _ = _serve(srv, pools, [R])
+    say("serve mix")
+    rng = np.random.default_rng(5)
+    mix = []
+    for k in range(30):
+        n = int(np.exp(rng.uniform(np.log(16), np.log(20000))))
+        off = int(rng.integers(0, POOL - n))
+        mix.append((off, n, int(rng.integers(1, LMAX + 1))))
+    mix.insert(12, R)
+    outs, _ = _serve(srv, pools, mix)
+    np.testing.assert_array_equal(outs[12], alone)
+    st = srv.stats()
+    assert st["completed"] == 32 and st["max_active_envs"] > R[1]
+    srv.close()
+    # the same request through mg_step (one fused launch of 20 control steps)
+    off, n, L = R
+    cls = pools["cls"][off:off + n]
+    sim = mgmod.Sim(CLASSES, n, DT, S, env_class=cls)
+    sim.reset(state=dev(pools["x0"][:, off:off + n]), param_mult=dev(pools["mult"][:, off:off + n]))
+    sim.step(dev(pools["act"][:L, :, off:off + n]))
+    np.testing.assert_array_equal(host(sim.get_state()), alone)
+    sim.close()
+    # and the FP64 oracle
+    ref = oracle.rollout(CLASSES, pools["x0"][:, off:off + n], pools["act"][:L, :, off:off + n], S,
+                         DT, env_class=cls, mult=pools["mult"][:, off:off + n])
+    assert rel_err(alone, ref["x"]) <= TOL_TRAJ
+
+
+def test_fifo_plain_baseline_same_results(mgmod, pools):
+    say("serve fifo")
+    reqs = [R, (50, 300, 7), (9000, 4100, 3)]
+    a = mgmod.Server(CLASSES, DT, S)
+    outs_a, _ = _serve(a, pools, reqs)
+    a.close()
+    b = mgmod.Server(CLASSES, DT, S, fifo_plain=True)
+    outs_b, _ = _serve(b, pools, reqs)
+    b.close()
+    for u, v in zip(outs_a, outs_b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_memory_cap_admission(mgmod, pools):
+    """A 20-page cap: requests wait for pages instead of failing; a request larger than the
+    whole cap is rejected at submit; no more pages than the cap are ever created."""
+    say("serve cap")
+    pb = mgmod.page_bytes(D)
+    srv = mgmod.Server(CLASSES, DT, S, mem_cap_bytes=20 * pb)
+    big = np.zeros((D, 3000), np.float32)
+    st, _ = srv.submit(out=big, **_req(pools, 0, 3000, 2))     # >= 47 pages
+    assert st == 1
+    reqs = [(k * 500, 400, 6) for k in range(8)]                # ~8 pages each
+    outs, _ = _serve(srv, pools, reqs)
+    s = srv.stats()
+    assert s["completed"] == 8 and s["rejected"] == 1
+    assert s["created_pages"] <= 20 and s["cap_pages"] == 20
+    srv.close()
+    ref = mgmod.Server(CLASSES, DT, S)
+    outs_ref, _ = _serve(ref, pools, reqs)
+    ref.close()
+    for u, v in zip(outs, outs_ref):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_request_joins_mid_flight(mgmod, pools):
+    """A short request submitted while a long one runs finishes first (continuous batching)."""
+    say("serve join")
+    srv = mgmod.Server(CLASSES, DT, S)
+    long_out = np.zeros((D, 30000), np.float32)
+    st, t_long = srv.submit(out=long_out, **_req(pools, 0, 30000, 64))
+    assert st == 0
+    t0 = time.time()
+    while srv.stats()["active_envs"] == 0 and time.time() - t0 < 30:
+        pass
+    short_out = np.zeros((D, 100), np.float32)
+    st, t_short = srv.submit(out=short_out, **_req(pools, 35000, 100, 1))
+    assert st == 0
+    assert srv.wait(t_short, 60_000_000)[0] == 0
+    still_running = srv.wait(t_long, 0)[0] == 5          # MG_ERR_BUSY
+    assert srv.wait(t_long, 60_000_000)[0] == 0
+    assert still_running
+    srv.close()
+
+
+def test_poisson_clients_all_complete(mgmod, pools):
+    """8 client threads, Poisson arrivals (aggregate 400 req/s for 0.5 s), log-uniform env
+    counts in [16, 4096], rollout lengths uniform in [1, 64]."""
+    say("serve poisson")
+    srv = mgmod.Server(CLASSES, DT, S)
+    rng = np.random.default_rng(9)
+    results = []
+    lock = threading.Lock()
+    t_start = mgmod.Server.clock_ns() + 20_000_000
+
+    def client(seed):
+        r = np.random.default_rng(seed)
+        t = t_start
+        while True:
+            t += int(r.exponential(1.0 / 50.0) * 1e9)
+            if t > t_start + 500_000_000:
+                break
+            n = int(np.exp(r.uniform(np.log(16), np.log(4096))))
+            L = int(r.integers(1, 65))
+            off = int(r.integers(0, POOL - n))
+            while mgmod.Server.clock_ns() < t:
+                time.sleep(0.0002)
+            out = np.zeros((D, n), np.float32)
+            st, tk = srv.submit(out=out, arrival_ns=t, **_req(pools, off, n, L))
+            with lock:
+                results.append((st, tk, out))
+
+    ths = [threading.Thread(target=client, args=(100 + i,)) for i in range(8)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    lats = []
+    for st, tk, out in results:
+        assert st == 0
+        st2, lat = srv.wait(tk, 60_000_000)
+        assert st2 == 0
+        lats.append(lat)
+        assert np.isfinite(out).all()
+    assert len(lats) > 100
+    assert srv.stats()["completed"] == len(lats)
+    srv.close()
+    assert 0 < np.percentile(lats, 50) <= np.percentile(lats, 99) < 30
+    assert rng is not None

@@ -245,6 +245,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one device copy of 1 GiB (read 1 GiB, write 1 GiB) whose "
+                         "FETCH_SIZE / WRITE_SIZE calibrate the counters of a --pmc run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the environments are independent and this "
@@ -265,6 +268,14 @@ def main():
     n_h = E - n_b
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # inputs, resident in HBM before timing
     x0 = torch.from_numpy(initial_state(E, 21, c.seed_base + 2)).to(dev)

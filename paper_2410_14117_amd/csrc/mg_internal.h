@@ -11,7 +11,10 @@ constexpr int kMaxThr = 8;
 constexpr int kNumParams = 23;
 constexpr int kNumDerived = 30;
 constexpr int kNumTheta = 19;
-constexpr int kBlock = 256;      // threads per block of the step kernels (4 wave64)
+#ifndef MG_BLOCK
+#define MG_BLOCK 256
+#endif
+constexpr int kBlock = MG_BLOCK; // threads per block of the step kernels (4 wave64)
 constexpr int kSegAlign = 64;    // each class segment starts on a wavefront boundary
 constexpr double kG0 = 9.81;
 

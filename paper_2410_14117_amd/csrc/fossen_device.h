@@ -52,6 +52,50 @@ __device__ __forceinline__ EnvConst load_env_const(const float* __restrict__ der
   return P;
 }
 
+// Uniform per-launch factors of the RK4 sub-step.  On gfx950 a VALU
+// instruction that reads a scalar register does not dual-issue, so the kernels
+// copy these into vector registers once (to_vgpr) and the sub-step's FMAs read
+// only vector registers.
+template <class T>
+struct StepConstT {
+  T h2, h2q, dt, dtq, h6, h6q;   // stage / combination factors; *q: quaternion rows (x 1/2)
+  T two;
+  T s2, s3, s4, rho;             // closed-form lag stage factors (ClassConst)
+};
+
+__device__ __forceinline__ float to_vgpr(float x) {
+  float r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+
+__device__ __forceinline__ StepConstT<float> make_step_const(const ClassConst& cc, float dt) {
+  StepConstT<float> k;
+  const float h2 = 0.5f * dt, h6 = dt * (1.0f / 6.0f);
+  k.h2 = to_vgpr(h2);
+  k.h2q = to_vgpr(0.5f * h2);
+  k.dt = to_vgpr(dt);
+  k.dtq = to_vgpr(0.5f * dt);
+  k.h6 = to_vgpr(h6);
+  k.h6q = to_vgpr(0.5f * h6);
+  k.two = to_vgpr(2.0f);
+  k.s2 = to_vgpr(cc.sigma2);
+  k.s3 = to_vgpr(cc.sigma3);
+  k.s4 = to_vgpr(cc.sigma4);
+  k.rho = to_vgpr(cc.rho);
+  return k;
+}
+
+// Host-side (double) version for checks of the kernel math.
+inline StepConstT<double> make_step_const_host(const ClassConst& cc, double dt) {
+  StepConstT<double> k;
+  const double h2 = 0.5 * dt, h6 = dt * (1.0 / 6.0);
+  k.h2 = h2; k.h2q = 0.5 * h2; k.dt = dt; k.dtq = 0.5 * dt; k.h6 = h6; k.h6q = 0.5 * h6;
+  k.two = 2.0;
+  k.s2 = cc.sigma2; k.s3 = cc.sigma3; k.s4 = cc.sigma4; k.rho = cc.rho;
+  return k;
+}
+
 // Per-env factorisation done once at reset: M = M_RB + M_A for diagonal I_g
 // and M_A with r_g = (0,0,z_g) couples only (u,q) and (v,p), so M^-1 is two
 // 2x2 inverses and two reciprocals; formed in FP64 from the parameters
@@ -191,8 +235,8 @@ __host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvCo
 template <int N, bool LAG, class T>
 __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P,
                                                      const ClassConst& cc, const T (&fcmd)[N],
-                                                     const T (&gcmd)[6], T dt) {
-  const T h2 = T(0.5) * dt, h6 = dt * (T(1) / T(6));
+                                                     const T (&gcmd)[6],
+                                                     const StepConstT<T>& sc) {
   T df[N], dg[6], tau[6];
   if constexpr (LAG) {
 #pragma unroll
@@ -209,45 +253,47 @@ __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P
 #pragma unroll
     for (int k = 0; k < 6; ++k) tau[k] = gcmd[k];
   }
-  // stage / combination factors; the quaternion rows of rhs_core are 2 q'
-  auto fac = [](int i, T f) { return (i >= 3 && i < 7) ? T(0.5) * f : f; };
+  // stage / combination factors per row; the quaternion rows of rhs_core are 2 q'
+  auto f2 = [&](int i) { return (i >= 3 && i < 7) ? sc.h2q : sc.h2; };
+  auto f1 = [&](int i) { return (i >= 3 && i < 7) ? sc.dtq : sc.dt; };
+  auto f6 = [&](int i) { return (i >= 3 && i < 7) ? sc.h6q : sc.h6; };
   T k[13], X[13], acc[13];
   rhs_core(x, k, P, tau);
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
     acc[i] = k[i];
-    X[i] = fma_t(fac(i, h2), k[i], x[i]);
+    X[i] = fma_t(f2(i), k[i], x[i]);
   }
   if constexpr (LAG) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) tau[j] = fma_t(T(cc.sigma2), dg[j], gcmd[j]);
+    for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s2, dg[j], gcmd[j]);
   }
   rhs_core(X, k, P, tau);
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
-    acc[i] = fma_t(T(2), k[i], acc[i]);
-    X[i] = fma_t(fac(i, h2), k[i], x[i]);
+    acc[i] = fma_t(sc.two, k[i], acc[i]);
+    X[i] = fma_t(f2(i), k[i], x[i]);
   }
   if constexpr (LAG) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) tau[j] = fma_t(T(cc.sigma3), dg[j], gcmd[j]);
+    for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s3, dg[j], gcmd[j]);
   }
   rhs_core(X, k, P, tau);
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
-    acc[i] = fma_t(T(2), k[i], acc[i]);
-    X[i] = fma_t(fac(i, dt), k[i], x[i]);
+    acc[i] = fma_t(sc.two, k[i], acc[i]);
+    X[i] = fma_t(f1(i), k[i], x[i]);
   }
   if constexpr (LAG) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) tau[j] = fma_t(T(cc.sigma4), dg[j], gcmd[j]);
+    for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s4, dg[j], gcmd[j]);
   }
   rhs_core(X, k, P, tau);
 #pragma unroll
-  for (int i = 0; i < 13; ++i) x[i] = fma_t(fac(i, h6), acc[i] + k[i], x[i]);
+  for (int i = 0; i < 13; ++i) x[i] = fma_t(f6(i), acc[i] + k[i], x[i]);
   if constexpr (LAG) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[13 + i] = fma_t(T(cc.rho), df[i], fcmd[i]);
+    for (int i = 0; i < N; ++i) x[13 + i] = fma_t(sc.rho, df[i], fcmd[i]);
   }
   const T n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
   const T inv = rsqrt_t(n2);

@@ -34,6 +34,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const Class
 #pragma unroll
   for (int i = 0; i < D; ++i) x[i] = a.state[i * a.Ep + j];
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
+  const StepConstT<float> sc = make_step_const(cc, a.dt);
   for (int t = 0; t < a.T; ++t) {
     if (t % a.ckpt_every == 0) {
       float* ck = a.ckpt + (int64_t)(t / a.ckpt_every) * a.D * a.E + c;
@@ -43,7 +44,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const Class
     }
     float act[N], fcmd[N], gcmd[6];
     load_command<N>(cc, a, t, c, act, fcmd, gcmd);
-    for (int s = 0; s < a.substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, a.dt);
+    for (int s = 0; s < a.substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, sc);
     if (a.traj) {
       float* tf = a.traj + (int64_t)t * a.D * a.E + c;
 #pragma unroll
@@ -63,6 +64,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const Class
   const int64_t j = a.seg_start + local;
   const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
+  const StepConstT<float> sc = make_step_const(cc, a.dt);
   const int K = a.ckpt_every, S = a.substeps;
   const int nseg = (a.T + K - 1) / K;
   float lam[D];
@@ -84,7 +86,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const Class
         float* sb = a.segbuf + (int64_t)((t - t0) * S + s) * D * a.Ep + j;
 #pragma unroll
         for (int i = 0; i < D; ++i) sb[i * a.Ep] = x[i];
-        rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, a.dt);
+        rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, sc);
       }
     }
     // reverse sweep over the segment

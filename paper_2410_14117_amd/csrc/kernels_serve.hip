@@ -43,6 +43,7 @@ __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickItem* __re
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   const int n = *count;
+  const StepConstT<float> sc = make_step_const(cc, dt);
   for (int e = wave; e < n; e += nwaves) {
     const ServeTickItem it = items[e];
     const int64_t col = it.cols[lane];
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickItem* __re
     for (int i = 0; i < N; ++i) act[i] = af[i * it.ld];
     thrust_command<N>(cc, act, fcmd);
     command_wrench<N>(cc, fcmd, gcmd);
-    for (int s = 0; s < substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dt);
+    for (int s = 0; s < substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, sc);
 #pragma unroll
     for (int i = 0; i < D; ++i) it.block[i * kPageEnvs + lane] = x[i];
   }

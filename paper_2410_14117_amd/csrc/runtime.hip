@@ -34,6 +34,11 @@ struct mg_sim {
   int device = 0;
   hipStream_t stream = nullptr;      // caller's stream (not owned)
   hipStream_t cap_stream = nullptr;  // owned, used only to capture graphs
+  // one helper stream per class after the first: the classes' launches are
+  // independent, so they run as parallel chains (fork/join through events) and
+  // one class's tail of blocks overlaps the other's
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> ev_fork, ev_join;
   bool broken = false;
   std::string err;
 
@@ -208,7 +213,8 @@ mg_status ensure_partials(mg_sim* s, int32_t n_ctrl) {
 }
 
 // Enqueue n_ctrl fused control steps (plain = 0) or their plain equivalent
-// (one launch per sub-step), followed by the statistics pass.
+// (one launch per sub-step), followed by the statistics pass.  Class k >= 1
+// runs on helper stream k-1, forked from and joined back into `st`.
 mg_status enqueue_steps(mg_sim* s, hipStream_t st, const float* actions, int32_t n_ctrl,
                         const float* targets, float* traj, double* stats, bool plain,
                         bool one_launch_per_ctrl) {
@@ -227,19 +233,24 @@ mg_status enqueue_steps(mg_sim* s, hipStream_t st, const float* actions, int32_t
   const int64_t frame = (int64_t)s->n_max * s->E;
   const int64_t tframe = (int64_t)s->D * s->E;
   const int64_t pframe = (int64_t)s->nblk_total * 4;
-  if (!plain && !one_launch_per_ctrl) {
-    a.actions = actions;
-    a.traj = traj;
-    a.partials = stats ? s->partials : nullptr;
-    a.n_ctrl = n_ctrl;
-    a.substeps = s->substeps;
-    for (int k = 0; k < s->n_classes; ++k) {
-      a.seg_start = s->seg_start[k];
-      a.seg_len = s->seg_len[k];
-      a.blk_off = s->seg_blk_off[k];
-      MG_HIP(s, launch_step(s->cc[k], a, st));
+  for (int k = 1; k < s->n_classes; ++k) {
+    MG_HIP(s, hipEventRecord(s->ev_fork[k - 1], st));
+    MG_HIP(s, hipStreamWaitEvent(s->aux[k - 1], s->ev_fork[k - 1], 0));
+  }
+  for (int k = 0; k < s->n_classes; ++k) {
+    hipStream_t ks = k == 0 ? st : s->aux[k - 1];
+    a.seg_start = s->seg_start[k];
+    a.seg_len = s->seg_len[k];
+    a.blk_off = s->seg_blk_off[k];
+    if (!plain && !one_launch_per_ctrl) {
+      a.actions = actions;
+      a.traj = traj;
+      a.partials = stats ? s->partials : nullptr;
+      a.n_ctrl = n_ctrl;
+      a.substeps = s->substeps;
+      MG_HIP(s, launch_step(s->cc[k], a, ks));
+      continue;
     }
-  } else {
     const int32_t n_sub = plain ? s->substeps : 1;
     for (int32_t t = 0; t < n_ctrl; ++t) {
       for (int32_t sub = 0; sub < n_sub; ++sub) {
@@ -249,14 +260,13 @@ mg_status enqueue_steps(mg_sim* s, hipStream_t st, const float* actions, int32_t
         a.partials = (stats && last) ? s->partials + t * pframe : nullptr;
         a.n_ctrl = 1;
         a.substeps = plain ? 1 : s->substeps;
-        for (int k = 0; k < s->n_classes; ++k) {
-          a.seg_start = s->seg_start[k];
-          a.seg_len = s->seg_len[k];
-          a.blk_off = s->seg_blk_off[k];
-          MG_HIP(s, launch_step(s->cc[k], a, st));
-        }
+        MG_HIP(s, launch_step(s->cc[k], a, ks));
       }
     }
+  }
+  for (int k = 1; k < s->n_classes; ++k) {
+    MG_HIP(s, hipEventRecord(s->ev_join[k - 1], s->aux[k - 1]));
+    MG_HIP(s, hipStreamWaitEvent(st, s->ev_join[k - 1], 0));
   }
   if (stats) MG_HIP(s, launch_stats_finalize(s->partials, s->nblk_total, n_ctrl, stats, st));
   return MG_OK;
@@ -473,6 +483,22 @@ mg_status mg_create(const mg_config* cfg, mg_sim** out) {
     (void)hipGetLastError();
     return bail(MG_ERR_DEVICE, "device initialisation failed in mg_create");
   }
+  for (int k = 1; k < s->n_classes; ++k) {
+    hipStream_t hs = nullptr;
+    hipEvent_t e1 = nullptr, e2 = nullptr;
+    if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      if (hs) s->aux.push_back(hs);
+      if (e1) s->ev_fork.push_back(e1);
+      if (e2) s->ev_join.push_back(e2);
+      return bail(MG_ERR_DEVICE, "helper stream creation failed in mg_create");
+    }
+    s->aux.push_back(hs);
+    s->ev_fork.push_back(e1);
+    s->ev_join.push_back(e2);
+  }
   if (reset_impl(s, nullptr, E, nullptr, nullptr, 0, 1) != MG_OK ||
       hipStreamSynchronize(s->stream) != hipSuccess) {
     (void)hipGetLastError();
@@ -489,6 +515,9 @@ void mg_destroy(mg_sim* s) {
     if (s->stream || s->state) (void)hipStreamSynchronize(s->stream);
     clear_graphs(s);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    for (hipStream_t h : s->aux) (void)hipStreamDestroy(h);
+    for (hipEvent_t e : s->ev_fork) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->ev_join) (void)hipEventDestroy(e);
     void* bufs[] = {s->state, s->params, s->derived, s->perm, s->iperm, s->class_of,
                     s->nominal_dev, s->partials, s->staging, s->segbuf};
     for (void* b : bufs)

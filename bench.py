@@ -36,11 +36,12 @@ def substep_flops(n_thr, lag, substeps):
     """Flops of one env-substep as the kernel formulates it (FMA = 2, one per add/mul):
     four right-hand sides of the rigid-body states (158 each), the RK4 stages and
     combination of the 13 rigid-body states (151), the quaternion renormalisation (12)
-    and, with a thruster lag, the closed-form lag stages (15 N + 36 - 12); plus the
-    per-control-step throttle map and command wrench (14 N - 6) spread over the sub-steps."""
+    and, with a thruster lag, the closed-form lag stages with the carried lag wrench
+    (3 N + 48); plus, per control step, the throttle map, the command wrench and the lag
+    wrench (27 N - 12; 14 N - 6 without lag) spread over the sub-steps."""
     core = 4 * 158 + 60 + 52 + 39 + 12
-    lag_part = (15 * n_thr + 36) if lag else 0
-    per_ctrl = 14 * n_thr - 6
+    lag_part = (3 * n_thr + 48) if lag else 0
+    per_ctrl = (27 * n_thr - 12) if lag else (14 * n_thr - 6)
     return core + lag_part + per_ctrl / substeps
 
 
@@ -98,12 +99,12 @@ def cpu_baseline(n_envs=8192, n_ctrl=200):
                       f"{c.substeps} RK4 sub-steps, FP64, with statistics; {dt:.2f} s"}
 
 
-def bench_adjoint(torch, mg, reps=5):
+def bench_adjoint(torch, mg, reps=5, n_envs=None):
     """C4: 8192 BlueROV2 envs, 64 control steps of 10 ms, checkpoint every 8; forward with
     checkpoints, backward (recompute + reverse sweep), against the plain per-step launch."""
     from workloads import BLUEROV2, CONFIGS, initial_state, actions
     c = CONFIGS["c4"]
-    E, T, K = c.n_envs, c.n_ctrl, c.extra["ckpt_every"]
+    E, T, K = n_envs or c.n_envs, c.n_ctrl, c.extra["ckpt_every"]
     dev = torch.device("cuda:0")
     x0 = torch.from_numpy(initial_state(E, 13, c.seed_base + 2)).to(dev)
     act = torch.from_numpy(actions(T, 6, E, c.seed_base + 3)).to(dev)
@@ -139,7 +140,9 @@ def bench_adjoint(torch, mg, reps=5):
 
     t_plain = timed(plain)
     sim.close()
-    return {"workload": "c4: 8192 BlueROV2 envs, 64 control steps of 10 ms, checkpoint every 8, "
+    del traj, g, act, ckpt
+    torch.cuda.empty_cache()
+    return {"workload": f"{E} BlueROV2 envs, 64 control steps of 10 ms, checkpoint every 8, "
                         "gradients w.r.t. throttles, 19 hydrodynamic parameters and x0",
             "forward_ms": t_fwd, "backward_ms": t_bwd, "fwd_plus_bwd_ms": t_fwd + t_bwd,
             "cost_vs_forward": (t_fwd + t_bwd) / t_fwd,
@@ -182,13 +185,15 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005):
             L = 1 if rng.random() < 0.5 else int(rng.integers(1, LMAX + 1))
             off = int(rng.integers(0, P - n + 1))
             trace.append((k, t, n, L, off))
-    per_client = [[r for r in trace if r[0] == k] for k in range(n_clients)]
+    # the 32 clients' Poisson streams merged into one arrival sequence, submitted by one
+    # thread at the scheduled times (open loop: latency counts from the scheduled arrival)
+    trace.sort(key=lambda r: r[1])
     results = []
-    lock = threading.Lock()
+    lags = []
     t0 = mg.Server.clock_ns() + 50_000_000
 
-    def client(reqs):
-        for _, t, n, L, off in reqs:
+    def submitter():
+        for _, t, n, L, off in trace:
             at = t0 + int(t * 1e9)
             while True:
                 wait_ns = at - mg.Server.clock_ns()
@@ -196,19 +201,17 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005):
                     break
                 if wait_ns > 300_000:
                     time.sleep((wait_ns - 200_000) * 1e-9)
+            lags.append(mg.Server.clock_ns() - at)
             out = np.empty((D, n), np.float32)
             st, tk = srv.submit(n, L, x0_d.data_ptr() + 4 * off, act_d.data_ptr() + 4 * off, P,
                                 out, env_class=cls[off:off + n],
                                 mult_ptr=mult_d.data_ptr() + 4 * off, arrival_ns=at)
-            with lock:
-                results.append((st, tk, n, L))
+            results.append((st, tk, n, L))
 
-    ths = [threading.Thread(target=client, args=(r,)) for r in per_client]
+    th = threading.Thread(target=submitter)
     w0 = time.perf_counter()
-    for th in ths:
-        th.start()
-    for th in ths:
-        th.join()
+    th.start()
+    th.join()
     lats, env_steps = [], 0
     for st, tk, n, L in results:
         if st != 0:
@@ -230,7 +233,66 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005):
             "p50_ms": float(np.percentile(lats, 50) * 1e3),
             "p99_ms": float(np.percentile(lats, 99) * 1e3),
             "p999_ms": float(np.percentile(lats, 99.9) * 1e3),
-            "max_active_envs": stats["max_active_envs"], "ticks": stats["ticks"]}
+            "max_active_envs": stats["max_active_envs"], "ticks": stats["ticks"],
+            "host_issue_us_per_tick": stats["issue_ns"] / max(1, stats["ticks"]) / 1e3,
+            "host_blocked_us_per_tick": stats["wait_ns"] / max(1, stats["ticks"]) / 1e3,
+            "queue_wait_mean_ms": stats["mean_queue_ns"] / 1e6,
+            "queue_wait_max_ms": stats["max_queue_ns"] / 1e6,
+            "submit_lag_p50_ms": float(np.percentile(lags, 50) / 1e6),
+            "submit_lag_p99_ms": float(np.percentile(lags, 99) / 1e6)}
+
+
+def summarise_profile(root):
+    """Summary of rocprofv3 CSV output under `root` (host-only, no GPU): per-kernel launch
+    statistics from kernel_stats.csv; for the k_step launches of a kernel trace the union of
+    their busy intervals per launch pair (the BlueROV2 and Heavy launches of one control or
+    sub-step run concurrently, so the pair's wall time is the figure comparable with the
+    bench's per-control-step time); per-kernel counter means from --pmc runs."""
+    import csv
+    import collections
+    import glob
+    out = []
+    for f in sorted(glob.glob(os.path.join(root, "**", "*kernel_stats.csv"), recursive=True)):
+        out.append(f"## {os.path.relpath(f, root)}")
+        out.append("| kernel | calls | avg (us) | min (us) | max (us) | share |")
+        out.append("|---|---|---|---|---|---|")
+        for r in csv.DictReader(open(f)):
+            out.append(f"| `{r['Name'][:100]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                       f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                       f"{float(r['Percentage']):.2f} % |")
+    for f in sorted(glob.glob(os.path.join(root, "**", "*kernel_trace.csv"), recursive=True)):
+        rows = list(csv.DictReader(open(f)))
+        out.append(f"## {os.path.relpath(f, root)}")
+        for label, plain in (("fused k_step", "false"), ("plain k_step", "true")):
+            ivs = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows
+                         if r["Kernel_Name"].startswith("void mg::k_step<")
+                         and r["Kernel_Name"].split(",")[2].strip().startswith(plain))
+            if not ivs:
+                continue
+            union, cs, ce = 0, None, None
+            for a, b in ivs:
+                if ce is None or a > ce:
+                    union += 0 if ce is None else ce - cs
+                    cs, ce = a, b
+                else:
+                    ce = max(ce, b)
+            union += ce - cs
+            mean = sum(b - a for a, b in ivs) / len(ivs)
+            out.append(f"{label}: {len(ivs)} launches, mean launch {mean / 1e3:.2f} us, union of "
+                       f"busy intervals {union / 1e3:.1f} us = {2 * union / len(ivs) / 1e3:.2f} us "
+                       f"per launch pair")
+    for f in sorted(glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True)):
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(f)):
+            agg[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        out.append(f"## {os.path.relpath(f, root)}")
+        out.append("| kernel | counter | dispatches | mean | min | max |")
+        out.append("|---|---|---|---|---|---|")
+        for k, cs_ in agg.items():
+            for cname, v in cs_.items():
+                out.append(f"| `{k[:80]}` | {cname} | {len(v)} | {sum(v) / len(v):.7g} | "
+                           f"{min(v):.7g} | {max(v):.7g} |")
+    return "\n".join(out)
 
 
 def main():
@@ -248,7 +310,12 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one device copy of 1 GiB (read 1 GiB, write 1 GiB) whose "
                          "FETCH_SIZE / WRITE_SIZE calibrate the counters of a --pmc run")
+    ap.add_argument("--summarise-profile", metavar="DIR",
+                    help="print a summary of the rocprofv3 CSV files under DIR and exit")
     args = ap.parse_args()
+    if args.summarise_profile:
+        print(summarise_profile(args.summarise_profile))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the environments are independent and this "
               "build runs no multi-GPU path; run with --gpus 1", file=sys.stderr)
@@ -318,7 +385,6 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     fused_ms = ev0.elapsed_time(ev1) / reps
-    launches = 2 * T
     flops_rollout = (n_b * substep_flops(6, True, S) + n_h * substep_flops(8, True, S)) * T * S
     achieved = flops_rollout / (fused_ms * 1e-3)
     st = stats.cpu().numpy()
@@ -337,9 +403,11 @@ def main():
         "sim_seconds_per_wall_second": value * c.dt_sub,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                     "traffic": load_traffic("k_step_fused"),
-                     "kernel": "k_step<6|8,lag> fused, 16 sub-steps per launch",
-                     "avg_launch_us": fused_ms * 1e3 / launches,
+                     "traffic": load_traffic("k_step_fused_control_step"),
+                     "kernel": "k_step<6|8,lag> fused: the BlueROV2 and Heavy launches of one "
+                               "control step (16 RK4 sub-steps each), run concurrently",
+                     "control_step_us": fused_ms * 1e3 / T,
+                     "flops_per_control_step": flops_rollout / T,
                      "flops_per_env_substep": {"bluerov2": substep_flops(6, True, S),
                                                "heavy": substep_flops(8, True, S)}},
         "stats_last_step": {"mean_dist": st[-1, 0] / max(1, E - st[-1, 3]),
@@ -371,6 +439,7 @@ def main():
 
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, mg)
+        out["adjoint_1m_envs"] = bench_adjoint(torch, mg, reps=3, n_envs=1 << 20)
     if not args.no_serve:
         cb = bench_serving(torch, mg, args.serve_seconds)
         base = bench_serving(torch, mg, args.serve_seconds, fifo_plain=True)

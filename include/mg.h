@@ -261,9 +261,14 @@ typedef struct {
   uint64_t arrival_ns;
 } mg_request;
 
+/* Server counters: requests completed / rejected, ticks issued, env control
+ * steps done, envs active now and at most, requests queued now, the page cap
+ * and pages created; host time spent issuing ticks and blocked waiting for the
+ * GPU (ns, summed); mean and max time from arrival to admission (ns). */
 typedef struct {
   int64_t completed, rejected, ticks, env_steps, active_envs, max_active_envs, queued;
   int64_t cap_pages, created_pages;
+  int64_t issue_ns, wait_ns, mean_queue_ns, max_queue_ns;
 } mg_server_stats;
 
 uint64_t mg_clock_ns(void);

@@ -228,27 +228,33 @@ __host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvCo
 // The thruster states enter only through the wrench B f and obey the linear
 // lag f' = (f_cmd - f) / tau with f_cmd held, so their RK4 stage values are
 // f_cmd + sigma_i (f - f_cmd) exactly (class constants), the stage wrenches
-// are B f_cmd + sigma_i B (f - f_cmd), and the sub-step maps f - f_cmd to
-// rho (f - f_cmd): the same discrete map as generic RK4 on the lag states,
-// with one allocation product per sub-step instead of four.  Without a lag
-// the wrench is the command wrench B f_cmd throughout.
+// are B f_cmd + sigma_i dg with dg = B (f - f_cmd), and the sub-step maps
+// f - f_cmd and dg alike to rho times themselves: the same discrete map as
+// generic RK4 on the lag states.  dg is carried from sub-step to sub-step of
+// a control step (formed once per control step by lag_wrench), so no
+// allocation product is needed inside the sub-step.  Without a lag the wrench
+// is the command wrench B f_cmd throughout.
+template <int N, class T>
+__host__ __device__ __forceinline__ void lag_wrench(const ClassConst& cc, const T* x,
+                                                    const T (&fcmd)[N], T (&dg)[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    T s = T(cc.B[k][0]) * (x[13] - fcmd[0]);
+#pragma unroll
+    for (int i = 1; i < N; ++i) s = fma_t(T(cc.B[k][i]), x[13 + i] - fcmd[i], s);
+    dg[k] = s;
+  }
+}
+
 template <int N, bool LAG, class T>
 __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P,
                                                      const ClassConst& cc, const T (&fcmd)[N],
-                                                     const T (&gcmd)[6],
+                                                     const T (&gcmd)[6], T (&dg)[6],
                                                      const StepConstT<T>& sc) {
-  T df[N], dg[6], tau[6];
+  T tau[6];
   if constexpr (LAG) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) df[i] = x[13 + i] - fcmd[i];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      T s = T(cc.B[k][0]) * df[0];
-#pragma unroll
-      for (int i = 1; i < N; ++i) s = fma_t(T(cc.B[k][i]), df[i], s);
-      dg[k] = s;
-      tau[k] = gcmd[k] + s;
-    }
+    for (int k = 0; k < 6; ++k) tau[k] = gcmd[k] + dg[k];
   } else {
 #pragma unroll
     for (int k = 0; k < 6; ++k) tau[k] = gcmd[k];
@@ -293,7 +299,9 @@ __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P
   for (int i = 0; i < 13; ++i) x[i] = fma_t(f6(i), acc[i] + k[i], x[i]);
   if constexpr (LAG) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[13 + i] = fma_t(sc.rho, df[i], fcmd[i]);
+    for (int i = 0; i < N; ++i) x[13 + i] = fma_t(sc.rho, x[13 + i] - fcmd[i], fcmd[i]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dg[k] *= sc.rho;
   }
   const T n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
   const T inv = rsqrt_t(n2);

@@ -42,9 +42,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const Class
       for (int i = 0; i < D; ++i) ck[i * a.E] = x[i];
       for (int i = D; i < a.D; ++i) ck[i * a.E] = 0.0f;
     }
-    float act[N], fcmd[N], gcmd[6];
+    float act[N], fcmd[N], gcmd[6], dg[6];
     load_command<N>(cc, a, t, c, act, fcmd, gcmd);
-    for (int s = 0; s < a.substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, sc);
+    if constexpr (LAG) lag_wrench<N>(cc, x, fcmd, dg);
+    for (int s = 0; s < a.substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, sc);
     if (a.traj) {
       float* tf = a.traj + (int64_t)t * a.D * a.E + c;
 #pragma unroll
@@ -80,13 +81,14 @@ __global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const Class
 #pragma unroll
     for (int i = 0; i < D; ++i) x[i] = ck[i * a.E];
     for (int t = t0; t < t1; ++t) {
-      float act[N], fcmd[N], gcmd[6];
+      float act[N], fcmd[N], gcmd[6], dg[6];
       load_command<N>(cc, a, t, c, act, fcmd, gcmd);
+      if constexpr (LAG) lag_wrench<N>(cc, x, fcmd, dg);
       for (int s = 0; s < S; ++s) {
         float* sb = a.segbuf + (int64_t)((t - t0) * S + s) * D * a.Ep + j;
 #pragma unroll
         for (int i = 0; i < D; ++i) sb[i * a.Ep] = x[i];
-        rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, sc);
+        rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, sc);
       }
     }
     // reverse sweep over the segment

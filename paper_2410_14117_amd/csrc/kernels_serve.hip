@@ -35,33 +35,51 @@ __global__ void __launch_bounds__(64) k_serve_init(const ServeInitItem* __restri
 
 template <int N, bool LAG>
 __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickItem* __restrict__ items,
-                                                       const int32_t* __restrict__ count,
-                                                       const ClassConst cc, int32_t Dmax,
-                                                       int32_t n_max, int32_t substeps, float dt) {
+                                                       const ServeTickHeader* __restrict__ hdr,
+                                                       int32_t cls, const ClassConst cc,
+                                                       int32_t Dmax, int32_t n_max,
+                                                       int32_t substeps, float dt) {
   constexpr int D = Dims<N, LAG>::D;
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  const int n = *count;
+  const int n = hdr->count[cls];
+  const int64_t tick = hdr->tick;
   const StepConstT<float> sc = make_step_const(cc, dt);
   for (int e = wave; e < n; e += nwaves) {
     const ServeTickItem it = items[e];
+    if (!it.block) continue;
     const int64_t col = it.cols[lane];
     if (col < 0) continue;
     float x[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) x[i] = it.block[i * kPageEnvs + lane];
     const EnvConst P = load_env_const(it.block + Dmax * kPageEnvs, kPageEnvs, lane);
-    const float* af = it.actions + (int64_t)it.step * n_max * it.ld + col;
+    const float* af = it.actions + (tick - it.t0) * n_max * it.ld + col;
     float act[N], fcmd[N], gcmd[6];
 #pragma unroll
     for (int i = 0; i < N; ++i) act[i] = af[i * it.ld];
     thrust_command<N>(cc, act, fcmd);
     command_wrench<N>(cc, fcmd, gcmd);
-    for (int s = 0; s < substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, sc);
+    float dg[6];
+    if constexpr (LAG) lag_wrench<N>(cc, x, fcmd, dg);
+    for (int s = 0; s < substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, sc);
 #pragma unroll
     for (int i = 0; i < D; ++i) it.block[i * kPageEnvs + lane] = x[i];
   }
+}
+
+__global__ void __launch_bounds__(256) k_serve_patch(const ServePatch* __restrict__ patches,
+                                                     int32_t n, ServeTickItem* __restrict__ list) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) list[patches[i].index] = patches[i].item;
+}
+
+hipError_t launch_serve_patch(const ServePatch* patches, int32_t n, ServeTickItem* list,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_serve_patch, dim3((n + 255) / 256), dim3(256), 0, s, patches, n, list);
+  return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(64) k_serve_gather(const ServeGatherItem* __restrict__ items,
@@ -81,22 +99,22 @@ hipError_t launch_serve_init(const ServeInitItem* items, int32_t n_items,
 }
 
 template <int N, bool LAG>
-static hipError_t tick_t(const ClassConst& cc, const ServeTickItem* items, const int32_t* count,
-                         int32_t Dmax, int32_t n_max, int32_t substeps, float dt, int32_t grid,
-                         hipStream_t s) {
-  hipLaunchKernelGGL((k_serve_tick<N, LAG>), dim3(grid), dim3(kBlock), 0, s, items, count, cc,
+static hipError_t tick_t(const ClassConst& cc, int32_t cls, const ServeTickItem* items,
+                         const ServeTickHeader* hdr, int32_t Dmax, int32_t n_max,
+                         int32_t substeps, float dt, int32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_serve_tick<N, LAG>), dim3(grid), dim3(kBlock), 0, s, items, hdr, cls, cc,
                      Dmax, n_max, substeps, dt);
   return hipGetLastError();
 }
 
-hipError_t launch_serve_tick(const ClassConst& cc, const ServeTickItem* items,
-                             const int32_t* count, int32_t Dmax, int32_t n_max, int32_t substeps,
-                             float dt, int32_t grid, hipStream_t s) {
+hipError_t launch_serve_tick(const ClassConst& cc, int32_t cls, const ServeTickItem* items,
+                             const ServeTickHeader* hdr, int32_t Dmax, int32_t n_max,
+                             int32_t substeps, float dt, int32_t grid, hipStream_t s) {
   const bool lag = cc.lag != 0;
-#define MG_CASE(n)                                                                          \
-  case n:                                                                                   \
-    return lag ? tick_t<n, true>(cc, items, count, Dmax, n_max, substeps, dt, grid, s)      \
-               : tick_t<n, false>(cc, items, count, Dmax, n_max, substeps, dt, grid, s);
+#define MG_CASE(n)                                                                            \
+  case n:                                                                                     \
+    return lag ? tick_t<n, true>(cc, cls, items, hdr, Dmax, n_max, substeps, dt, grid, s)     \
+               : tick_t<n, false>(cc, cls, items, hdr, Dmax, n_max, substeps, dt, grid, s);
   switch (cc.n_thr) {
     MG_CASE(1) MG_CASE(2) MG_CASE(3) MG_CASE(4) MG_CASE(5) MG_CASE(6) MG_CASE(7) MG_CASE(8)
     default:

@@ -122,13 +122,20 @@ struct ServeInitItem {         // one newly admitted page
   int32_t cls;
   int32_t pad_;
 };
-struct ServeTickItem {         // one active page, one control step
-  float* block;
+struct ServeTickItem {         // one active page (device-resident list entry)
+  float* block;                // NULL: an empty entry
   const int32_t* cols;
   const float* actions;        // request [L][n_max][ld]
   int64_t ld;
-  int32_t step;
-  int32_t pad_;
+  int64_t t0;                  // tick of the request's first control step
+};
+struct ServeTickHeader {       // per tick: entries in use per class and the tick number
+  int32_t count[16];
+  int64_t tick;
+};
+struct ServePatch {            // one write into the device-resident tick list
+  int64_t index;               // cls * capacity + entry
+  ServeTickItem item;
 };
 struct ServeGatherItem {       // one page of a finished request
   const float* block;
@@ -139,10 +146,12 @@ struct ServeGatherItem {       // one page of a finished request
 hipError_t launch_serve_init(const ServeInitItem* items, int32_t n_items,
                              const ClassNominal* nominal, int32_t Dmax, hipStream_t s);
 // grid is fixed (persistent) so the launch can live in a replayed graph; the
-// number of items is read from *count on the device
-hipError_t launch_serve_tick(const ClassConst& cc, const ServeTickItem* items,
-                             const int32_t* count, int32_t Dmax, int32_t n_max, int32_t substeps,
-                             float dt, int32_t grid, hipStream_t s);
+// number of entries and the tick number are read from the header on the device
+hipError_t launch_serve_tick(const ClassConst& cc, int32_t cls, const ServeTickItem* items,
+                             const ServeTickHeader* hdr, int32_t Dmax, int32_t n_max,
+                             int32_t substeps, float dt, int32_t grid, hipStream_t s);
+hipError_t launch_serve_patch(const ServePatch* patches, int32_t n, ServeTickItem* list,
+                              hipStream_t s);
 hipError_t launch_serve_gather(const ServeGatherItem* items, int32_t n_items, int32_t Dmax,
                                hipStream_t s);
 

@@ -22,6 +22,7 @@
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <unordered_map>
@@ -54,6 +55,8 @@ struct Request {
   std::vector<int64_t> pages;
   std::vector<int32_t> page_cls;
   std::vector<int32_t> cols;         // [pages][64]
+  std::vector<int32_t> entry;        // per page: its entry in the class's tick list
+  int64_t t0 = 0;                    // tick of its first control step
 };
 
 struct Record {
@@ -114,15 +117,35 @@ struct mg_server {
     return slab_cols[p / slab_pages] + (p % slab_pages) * kPageEnvs;
   }
 
-  // per-tick lists
-  Mirror<ServeInitItem> init;
-  Mirror<int32_t> cols_stage;
-  Mirror<ServeTickItem> tick;      // n_classes regions of tick_cap entries
-  Mirror<int32_t> counts;
-  Mirror<ServeGatherItem> gather;
-  Mirror<float> out;
-  size_t tick_cap = 0;
-  hipGraphExec_t graph = nullptr;
+  // ring of tick slots: each holds the staging buffers, graph and event of one
+  // tick in flight, so the host builds tick k+1 while the GPU runs tick k
+  struct Slot {
+    Mirror<ServeInitItem> init;
+    Mirror<int32_t> cols_stage;
+    Mirror<ServeTickHeader> hdr;
+    Mirror<ServePatch> pre, post;    // list writes before / after this tick's kernels
+    Mirror<ServeGatherItem> gather;
+    Mirror<float>* out = nullptr;     // pooled pinned buffer of this tick's finished requests
+    hipGraphExec_t graph = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<Request*> retiring;   // finished by this tick, delivered on completion
+  };
+  struct Delivery {
+    std::vector<Request*> reqs;
+    Mirror<float>* out;
+  };
+  static constexpr int kSlots = 3;
+  Slot slots[kSlots];
+  std::deque<int> inflight;           // slot indices in issue order
+  int next_slot = 0;
+  int64_t tick_no = 0;
+
+  // device-resident tick list: per class list_cap entries (a page's entry stays
+  // put while its request runs); entries are reused lowest index first
+  ServeTickItem* list_d = nullptr;
+  size_t list_cap = 0;
+  std::vector<std::set<int32_t>> free_entries;
+  std::vector<int32_t> hw;            // per class: entries in use are below hw
   int32_t grid = 1024;
 
   // queue, records, thread
@@ -136,10 +159,20 @@ struct mg_server {
   bool broken = false;
   std::string err;
   std::thread thr;
+  // delivery thread: copies finished requests' states to the clients, frees their
+  // pages and completes them, off the scheduler thread
+  std::thread deliver_thr;
+  std::mutex dmu;
+  std::condition_variable dcv, dcv_done;
+  std::deque<Delivery> deliver_q;
+  std::vector<Mirror<float>*> out_pool;   // free pinned result buffers (guarded by dmu)
+  std::vector<Mirror<float>*> out_all;    // every result buffer, for teardown
+  bool deliver_stop = false;
 
   // statistics
   std::atomic<int64_t> completed{0}, rejected{0}, ticks{0}, env_steps{0}, active_envs{0},
       max_active_envs{0}, queued{0};
+  std::atomic<int64_t> issue_ns{0}, wait_ns{0}, queue_ns{0}, max_queue_ns{0}, admitted_n{0};
 };
 
 namespace {
@@ -201,10 +234,10 @@ ClassNominal class_nominal(const mg_vehicle& v) {
 // (Re)captures the tick graph: one persistent launch per class (fused: one
 // control step of `substeps` sub-steps; FIFO baseline: `substeps` plain
 // launches of one sub-step), reading its items and count from fixed buffers.
-bool capture_tick_graph(mg_server* S) {
-  if (S->graph) {
-    (void)hipGraphExecDestroy(S->graph);
-    S->graph = nullptr;
+bool capture_tick_graph(mg_server* S, mg_server::Slot& sl) {
+  if (sl.graph) {
+    (void)hipGraphExecDestroy(sl.graph);
+    sl.graph = nullptr;
   }
   hipStream_t cap;
   SV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -214,7 +247,7 @@ bool capture_tick_graph(mg_server* S) {
   const int sub = S->fifo_plain ? 1 : S->substeps;
   for (int r = 0; r < reps && e == hipSuccess; ++r)
     for (int c = 0; c < S->n_classes && e == hipSuccess; ++c)
-      e = launch_serve_tick(S->cc[c], S->tick.d + (size_t)c * S->tick_cap, S->counts.d + c, S->D,
+      e = launch_serve_tick(S->cc[c], c, S->list_d + (size_t)c * S->list_cap, sl.hdr.d, S->D,
                             S->n_max, sub, (float)S->dt, S->grid, cap);
   hipError_t e2 = hipStreamEndCapture(cap, &g);
   (void)hipStreamDestroy(cap);
@@ -222,7 +255,7 @@ bool capture_tick_graph(mg_server* S) {
     if (g) (void)hipGraphDestroy(g);
     return fail_server(S, "tick graph capture failed");
   }
-  hipError_t e3 = hipGraphInstantiate(&S->graph, g, nullptr, nullptr, 0);
+  hipError_t e3 = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e3 != hipSuccess) return fail_server(S, "tick graph instantiate failed");
   return true;
@@ -242,117 +275,12 @@ void finish(mg_server* S, Request* r, mg_status st) {
   delete r;
 }
 
-// One tick: initialise admitted pages, advance every active page one control
-// step, retire finished requests.  Returns false on a device error.
-bool tick(mg_server* S, std::vector<Request*>& admitted) {
-  // 1. newly admitted pages
-  size_t n_init = 0;
-  for (Request* r : admitted) n_init += r->pages.size();
-  if (n_init) {
-    if (!S->init.grow(n_init) || !S->cols_stage.grow(n_init * kPageEnvs))
-      return fail_server(S, "host/device staging allocation failed");
-    size_t k = 0;
-    for (Request* r : admitted) {
-      for (size_t p = 0; p < r->pages.size(); ++p, ++k) {
-        ServeInitItem& it = S->init.h[k];
-        std::memcpy(S->cols_stage.h + k * kPageEnvs, r->cols.data() + p * kPageEnvs,
-                    kPageEnvs * sizeof(int32_t));
-        it.block = S->page_block(r->pages[p]);
-        it.cols_src = S->cols_stage.d + k * kPageEnvs;
-        it.cols = S->page_cols(r->pages[p]);
-        it.x0 = r->x0;
-        it.mult = r->mult;
-        it.ld = r->ld;
-        it.cls = r->page_cls[p];
-        it.pad_ = 0;
-      }
-    }
-    SV_HIP(hipMemcpyAsync(S->cols_stage.d, S->cols_stage.h, n_init * kPageEnvs * sizeof(int32_t),
-                          hipMemcpyHostToDevice, S->stream));
-    SV_HIP(hipMemcpyAsync(S->init.d, S->init.h, n_init * sizeof(ServeInitItem),
-                          hipMemcpyHostToDevice, S->stream));
-    SV_HIP(launch_serve_init(S->init.d, (int32_t)n_init, S->nominal_dev, S->D, S->stream));
-    for (Request* r : admitted) S->active.push_back(r);
-    admitted.clear();
-  }
-
-  // 2. the tick itself
-  std::vector<size_t> per(S->n_classes, 0);
-  for (Request* r : S->active)
-    for (int32_t c : r->page_cls) ++per[c];
-  size_t need = 0;
-  for (size_t v : per) need = std::max(need, v);
-  if (need > S->tick_cap) {
-    SV_HIP(hipStreamSynchronize(S->stream));
-    const size_t cap = std::max<size_t>(need, 2 * S->tick_cap + 256);
-    if (!S->tick.grow(cap * S->n_classes)) return fail_server(S, "tick list allocation failed");
-    S->tick_cap = cap;
-    if (!capture_tick_graph(S)) return false;
-  }
-  std::vector<size_t> fill(S->n_classes, 0);
-  int64_t envs = 0;
-  for (Request* r : S->active) {
-    for (size_t p = 0; p < r->pages.size(); ++p) {
-      const int32_t c = r->page_cls[p];
-      ServeTickItem& it = S->tick.h[(size_t)c * S->tick_cap + fill[c]++];
-      it.block = S->page_block(r->pages[p]);
-      it.cols = S->page_cols(r->pages[p]);
-      it.actions = r->actions;
-      it.ld = r->ld;
-      it.step = r->step;
-      it.pad_ = 0;
-    }
-    envs += r->n;
-  }
-  for (int c = 0; c < S->n_classes; ++c) S->counts.h[c] = (int32_t)fill[c];
-  for (int c = 0; c < S->n_classes; ++c)
-    if (fill[c])
-      SV_HIP(hipMemcpyAsync(S->tick.d + (size_t)c * S->tick_cap, S->tick.h + (size_t)c * S->tick_cap,
-                            fill[c] * sizeof(ServeTickItem), hipMemcpyHostToDevice, S->stream));
-  SV_HIP(hipMemcpyAsync(S->counts.d, S->counts.h, S->n_classes * sizeof(int32_t),
-                        hipMemcpyHostToDevice, S->stream));
-  SV_HIP(hipGraphLaunch(S->graph, S->stream));
-  S->active_envs.store(envs);
-  if (envs > S->max_active_envs.load()) S->max_active_envs.store(envs);
-  S->env_steps.fetch_add(envs);
-  S->ticks.fetch_add(1);
-
-  // 3. retire the requests whose last control step this was
-  std::vector<Request*> done, keep;
-  for (Request* r : S->active) {
-    ++r->step;
-    (r->step >= r->L ? done : keep).push_back(r);
-  }
-  S->active.swap(keep);
-  size_t n_gat = 0, n_out = 0;
-  for (Request* r : done) {
-    n_gat += r->pages.size();
-    n_out += (size_t)r->n * S->D;
-  }
-  if (!done.empty()) {
-    if (!S->gather.grow(n_gat) || !S->out.grow(n_out))
-      return fail_server(S, "gather staging allocation failed");
-    size_t k = 0, o = 0;
-    for (Request* r : done) {
-      for (size_t p = 0; p < r->pages.size(); ++p, ++k) {
-        ServeGatherItem& it = S->gather.h[k];
-        it.block = S->page_block(r->pages[p]);
-        it.cols = S->page_cols(r->pages[p]);
-        it.out = S->out.d + o;
-        it.n = r->n;
-      }
-      o += (size_t)r->n * S->D;
-    }
-    SV_HIP(hipMemcpyAsync(S->gather.d, S->gather.h, n_gat * sizeof(ServeGatherItem),
-                          hipMemcpyHostToDevice, S->stream));
-    SV_HIP(launch_serve_gather(S->gather.d, (int32_t)n_gat, S->D, S->stream));
-    SV_HIP(hipMemcpyAsync(S->out.h, S->out.d, n_out * sizeof(float), hipMemcpyDeviceToHost,
-                          S->stream));
-  }
-  SV_HIP(hipStreamSynchronize(S->stream));
+// Deliver the requests that finished in a completed tick: copy their states
+// from the pinned result buffer to the clients, free their pages, complete them.
+void deliver(mg_server* S, mg_server::Delivery& d) {
   size_t o = 0;
-  for (Request* r : done) {
-    std::memcpy(r->out, S->out.h + o, (size_t)r->n * S->D * sizeof(float));
+  for (Request* r : d.reqs) {
+    std::memcpy(r->out, d.out->h + o, (size_t)r->n * S->D * sizeof(float));
     o += (size_t)r->n * S->D;
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -360,22 +288,238 @@ bool tick(mg_server* S, std::vector<Request*>& admitted) {
     }
     finish(S, r, MG_OK);
   }
+  std::lock_guard<std::mutex> lk(S->dmu);
+  S->out_pool.push_back(d.out);
+}
+
+Mirror<float>* take_out_buffer(mg_server* S) {
+  std::lock_guard<std::mutex> lk(S->dmu);
+  if (!S->out_pool.empty()) {
+    Mirror<float>* m = S->out_pool.back();
+    S->out_pool.pop_back();
+    return m;
+  }
+  S->out_all.push_back(new Mirror<float>());
+  return S->out_all.back();
+}
+
+// Grows the device tick list to hold `need` entries per class: waits for the
+// stream, copies the host mirror and re-captures every slot's graph.
+bool grow_list(mg_server* S, size_t need, std::vector<ServeTickItem>& host) {
+  size_t cap = std::max<size_t>(need, 2 * S->list_cap + 256);
+  SV_HIP(hipStreamSynchronize(S->stream));
+  std::vector<ServeTickItem> nh(cap * S->n_classes);
+  std::memset(nh.data(), 0, nh.size() * sizeof(ServeTickItem));
+  for (int c = 0; c < S->n_classes; ++c)
+    for (size_t e = 0; e < S->list_cap; ++e) nh[c * cap + e] = host[c * S->list_cap + e];
+  ServeTickItem* d = nullptr;
+  SV_HIP(hipMalloc(&d, nh.size() * sizeof(ServeTickItem)));
+  SV_HIP(hipMemcpy(d, nh.data(), nh.size() * sizeof(ServeTickItem), hipMemcpyHostToDevice));
+  if (S->list_d) SV_HIP(hipFree(S->list_d));
+  S->list_d = d;
+  S->list_cap = cap;
+  host.swap(nh);
+  for (auto& sl : S->slots)
+    if (!capture_tick_graph(S, sl)) return false;
   return true;
+}
+
+// Enqueue one tick into a free slot: initialise admitted pages and enter them
+// in the tick list, advance every active page one control step, gather the
+// requests whose last step this is into the slot's pinned buffer and empty
+// their list entries; record the slot's event.  Host work is proportional to
+// the pages that join or leave, not to the pages in flight.
+bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admitted,
+                 std::vector<ServeTickItem>& list_h) {
+  // 1. newly admitted pages: list entries first (the list may grow), then patches
+  size_t n_init = 0;
+  for (Request* r : admitted) n_init += r->pages.size();
+  if (n_init) {
+    for (Request* r : admitted) {
+      r->entry.resize(r->pages.size());
+      for (size_t p = 0; p < r->pages.size(); ++p) {
+        const int32_t c = r->page_cls[p];
+        auto& fe = S->free_entries[c];
+        int32_t e;
+        if (!fe.empty()) {
+          e = *fe.begin();
+          fe.erase(fe.begin());
+        } else {
+          e = S->hw[c]++;
+        }
+        r->entry[p] = e;
+      }
+    }
+    size_t need = 0;
+    for (int c = 0; c < S->n_classes; ++c) need = std::max<size_t>(need, S->hw[c]);
+    if (need > S->list_cap && !grow_list(S, need, list_h)) return false;
+    if (!sl.init.grow(n_init) || !sl.cols_stage.grow(n_init * kPageEnvs) || !sl.pre.grow(n_init))
+      return fail_server(S, "host/device staging allocation failed");
+    size_t k = 0;
+    for (Request* r : admitted) {
+      r->t0 = S->tick_no;
+      for (size_t p = 0; p < r->pages.size(); ++p, ++k) {
+        ServeInitItem& it = sl.init.h[k];
+        std::memcpy(sl.cols_stage.h + k * kPageEnvs, r->cols.data() + p * kPageEnvs,
+                    kPageEnvs * sizeof(int32_t));
+        it.block = S->page_block(r->pages[p]);
+        it.cols_src = sl.cols_stage.d + k * kPageEnvs;
+        it.cols = S->page_cols(r->pages[p]);
+        it.x0 = r->x0;
+        it.mult = r->mult;
+        it.ld = r->ld;
+        it.cls = r->page_cls[p];
+        it.pad_ = 0;
+        ServePatch& pt = sl.pre.h[k];
+        pt.index = (int64_t)r->page_cls[p] * (int64_t)S->list_cap + r->entry[p];
+        pt.item.block = it.block;
+        pt.item.cols = it.cols;
+        pt.item.actions = r->actions;
+        pt.item.ld = r->ld;
+        pt.item.t0 = r->t0;
+        list_h[pt.index] = pt.item;
+      }
+    }
+    SV_HIP(hipMemcpyAsync(sl.cols_stage.d, sl.cols_stage.h, n_init * kPageEnvs * sizeof(int32_t),
+                          hipMemcpyHostToDevice, S->stream));
+    SV_HIP(hipMemcpyAsync(sl.init.d, sl.init.h, n_init * sizeof(ServeInitItem),
+                          hipMemcpyHostToDevice, S->stream));
+    SV_HIP(launch_serve_init(sl.init.d, (int32_t)n_init, S->nominal_dev, S->D, S->stream));
+    SV_HIP(hipMemcpyAsync(sl.pre.d, sl.pre.h, n_init * sizeof(ServePatch), hipMemcpyHostToDevice,
+                          S->stream));
+    SV_HIP(launch_serve_patch(sl.pre.d, (int32_t)n_init, S->list_d, S->stream));
+    for (Request* r : admitted) S->active.push_back(r);
+    admitted.clear();
+  }
+
+  // 2. the tick itself
+  int64_t envs = 0;
+  for (Request* r : S->active) envs += r->n;
+  std::memset(sl.hdr.h, 0, sizeof(ServeTickHeader));
+  for (int c = 0; c < S->n_classes; ++c) sl.hdr.h->count[c] = S->hw[c];
+  sl.hdr.h->tick = S->tick_no;
+  SV_HIP(hipMemcpyAsync(sl.hdr.d, sl.hdr.h, sizeof(ServeTickHeader), hipMemcpyHostToDevice,
+                        S->stream));
+  SV_HIP(hipGraphLaunch(sl.graph, S->stream));
+  S->active_envs.store(envs);
+  if (envs > S->max_active_envs.load()) S->max_active_envs.store(envs);
+  S->env_steps.fetch_add(envs);
+  S->ticks.fetch_add(1);
+  ++S->tick_no;
+
+  // 3. the requests whose last control step this was
+  std::vector<Request*> keep;
+  for (Request* r : S->active) {
+    ++r->step;
+    (r->step >= r->L ? sl.retiring : keep).push_back(r);
+  }
+  S->active.swap(keep);
+  size_t n_gat = 0, n_out = 0;
+  for (Request* r : sl.retiring) {
+    n_gat += r->pages.size();
+    n_out += (size_t)r->n * S->D;
+  }
+  if (!sl.retiring.empty()) {
+    sl.out = take_out_buffer(S);
+    if (!sl.gather.grow(n_gat) || !sl.out->grow(n_out) || !sl.post.grow(n_gat))
+      return fail_server(S, "gather staging allocation failed");
+    size_t k = 0, o = 0;
+    for (Request* r : sl.retiring) {
+      for (size_t p = 0; p < r->pages.size(); ++p, ++k) {
+        ServeGatherItem& it = sl.gather.h[k];
+        it.block = S->page_block(r->pages[p]);
+        it.cols = S->page_cols(r->pages[p]);
+        it.out = sl.out->d + o;
+        it.n = r->n;
+        ServePatch& pt = sl.post.h[k];
+        const int32_t c = r->page_cls[p];
+        pt.index = (int64_t)c * (int64_t)S->list_cap + r->entry[p];
+        std::memset(&pt.item, 0, sizeof(pt.item));
+        list_h[pt.index] = pt.item;
+        S->free_entries[c].insert(r->entry[p]);
+      }
+      o += (size_t)r->n * S->D;
+    }
+    // the list shrinks from the top as its last entries empty
+    for (int c = 0; c < S->n_classes; ++c) {
+      auto& fe = S->free_entries[c];
+      while (S->hw[c] > 0 && !fe.empty() && *fe.rbegin() == S->hw[c] - 1) {
+        fe.erase(std::prev(fe.end()));
+        --S->hw[c];
+      }
+    }
+    SV_HIP(hipMemcpyAsync(sl.gather.d, sl.gather.h, n_gat * sizeof(ServeGatherItem),
+                          hipMemcpyHostToDevice, S->stream));
+    SV_HIP(launch_serve_gather(sl.gather.d, (int32_t)n_gat, S->D, S->stream));
+    SV_HIP(hipMemcpyAsync(sl.out->h, sl.out->d, n_out * sizeof(float), hipMemcpyDeviceToHost,
+                          S->stream));
+    SV_HIP(hipMemcpyAsync(sl.post.d, sl.post.h, n_gat * sizeof(ServePatch), hipMemcpyHostToDevice,
+                          S->stream));
+    SV_HIP(launch_serve_patch(sl.post.d, (int32_t)n_gat, S->list_d, S->stream));
+  }
+  SV_HIP(hipEventRecord(sl.ev, S->stream));
+  return true;
+}
+
+// Completes the oldest tick in flight; `block` waits for it, otherwise only a
+// finished one is taken.  Returns false on a device error.
+bool retire_oldest(mg_server* S, bool block, bool* took) {
+  *took = false;
+  if (S->inflight.empty()) return true;
+  mg_server::Slot& sl = S->slots[S->inflight.front()];
+  const uint64_t t_wait = clock_ns();
+  hipError_t e = block ? hipEventSynchronize(sl.ev) : hipEventQuery(sl.ev);
+  if (block) S->wait_ns.fetch_add((int64_t)(clock_ns() - t_wait));
+  if (e == hipErrorNotReady) return true;
+  if (e != hipSuccess) return fail_server(S, std::string("tick: ") + hipGetErrorString(e));
+  S->inflight.pop_front();
+  if (!sl.retiring.empty()) {
+    std::lock_guard<std::mutex> lk(S->dmu);
+    S->deliver_q.push_back(mg_server::Delivery{std::move(sl.retiring), sl.out});
+    sl.retiring.clear();
+    sl.out = nullptr;
+    S->dcv.notify_one();
+  }
+  *took = true;
+  return true;
+}
+
+void deliverer(mg_server* S) {
+  for (;;) {
+    mg_server::Delivery d;
+    {
+      std::unique_lock<std::mutex> lk(S->dmu);
+      S->dcv.wait(lk, [&] { return S->deliver_stop || !S->deliver_q.empty(); });
+      if (S->deliver_q.empty()) return;
+      d = std::move(S->deliver_q.front());
+      S->deliver_q.pop_front();
+    }
+    deliver(S, d);
+  }
 }
 
 void scheduler(mg_server* S) {
   (void)hipSetDevice(S->device);
   std::vector<Request*> admitted;
+  std::vector<ServeTickItem> list_h(S->list_cap * S->n_classes);
+  std::memset(list_h.data(), 0, list_h.size() * sizeof(ServeTickItem));
+  bool ok = true;
   for (;;) {
+    // deliver every tick the GPU has finished
+    bool took = true;
+    while (ok && took) ok = retire_oldest(S, false, &took);
+    if (!ok) break;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      if (S->active.empty()) {
+      if (S->active.empty() && S->inflight.empty()) {
         S->cv_sched.wait(lk, [&] { return S->stop || !S->queue.empty(); });
         if (S->queue.empty() && S->stop) break;
       }
-      // FIFO admission while the pages fit under the cap (FIFO baseline: one at a time)
+      // FIFO admission while the pages fit under the cap (FIFO baseline: one request
+      // at a time, the next admitted only once the previous one is delivered)
       while (!S->queue.empty() && !S->broken) {
-        if (S->fifo_plain && (!S->active.empty() || !admitted.empty())) break;
+        if (S->fifo_plain && (!S->active.empty() || !admitted.empty() || !S->inflight.empty()))
+          break;
         Request* r = S->queue.front();
         const int64_t need = PagePool::pages_for(r->per_class);
         if (!S->pool->fits(need)) break;
@@ -383,7 +527,7 @@ void scheduler(mg_server* S) {
         if (!S->pool->allocate(need, pages)) {
           // the cap allows it but device memory could not be obtained: with nothing
           // in flight to free pages, this request cannot make progress
-          if (!S->active.empty() || !admitted.empty()) break;
+          if (!S->active.empty() || !admitted.empty() || !S->inflight.empty()) break;
           S->queue.pop_front();
           S->queued.fetch_sub(1);
           lk.unlock();
@@ -393,38 +537,53 @@ void scheduler(mg_server* S) {
         }
         S->queue.pop_front();
         S->queued.fetch_sub(1);
-        // pages per class in class order; lanes take the class's envs in request order
-        r->pages = pages;
-        r->page_cls.clear();
-        r->cols.assign(pages.size() * kPageEnvs, -1);
-        size_t p = 0;
-        for (int c = 0; c < S->n_classes; ++c) {
-          int lane = 0;
-          if (r->per_class[c] == 0) continue;
-          r->page_cls.push_back(c);
-          for (int64_t e = 0; e < r->n; ++e) {
-            if (r->cls[e] != c) continue;
-            if (lane == kPageEnvs) {
-              lane = 0;
-              ++p;
-              r->page_cls.push_back(c);
-            }
-            r->cols[p * kPageEnvs + lane++] = (int32_t)e;
-          }
-          ++p;
+        {
+          const int64_t qw = (int64_t)(clock_ns() - r->arrival);
+          S->queue_ns.fetch_add(qw);
+          S->admitted_n.fetch_add(1);
+          if (qw > S->max_queue_ns.load()) S->max_queue_ns.store(qw);
         }
+        r->pages = pages;
         admitted.push_back(r);
       }
-      if (S->broken) {
-        lk.unlock();
-        break;
-      }
+      if (S->broken) break;
     }
-    if (admitted.empty() && S->active.empty()) continue;
-    if (!tick(S, admitted)) break;
+    if (admitted.empty() && S->active.empty()) {
+      // nothing to issue: wait for the oldest tick in flight (if any)
+      if (!S->inflight.empty()) ok = retire_oldest(S, true, &took);
+      if (!ok) break;
+      continue;
+    }
+    // a free slot: the ring's oldest tick must have completed
+    if ((int)S->inflight.size() == mg_server::kSlots) {
+      ok = retire_oldest(S, true, &took);
+      if (!ok) break;
+    }
+    const int k = S->next_slot;
+    S->next_slot = (S->next_slot + 1) % mg_server::kSlots;
+    const uint64_t t_issue = clock_ns();
+    if (!launch_tick(S, S->slots[k], admitted, list_h)) break;
+    S->issue_ns.fetch_add((int64_t)(clock_ns() - t_issue));
+    S->inflight.push_back(k);
   }
   // drain: anything left fails (device error or shutdown)
   const mg_status st = S->broken ? MG_ERR_DEVICE : MG_ERR_BUSY;
+  if (!S->broken) {
+    bool took = true;
+    while (!S->inflight.empty() && took && retire_oldest(S, true, &took)) {
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(S->dmu);
+    S->deliver_stop = true;
+  }
+  S->dcv.notify_all();
+  if (S->deliver_thr.joinable()) S->deliver_thr.join();
+  for (int k : S->inflight) {
+    for (Request* r : S->slots[k].retiring) finish(S, r, st);
+    S->slots[k].retiring.clear();
+  }
+  S->inflight.clear();
   for (Request* r : admitted) finish(S, r, st);
   for (Request* r : S->active) finish(S, r, st);
   S->active.clear();
@@ -517,20 +676,60 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc(&S->nominal_dev, sizeof(ClassNominal) * S->n_classes) != hipSuccess ||
       hipMemcpy(S->nominal_dev, S->nominal.data(), sizeof(ClassNominal) * S->n_classes,
-                hipMemcpyHostToDevice) != hipSuccess ||
-      !S->counts.grow(MG_MAX_CLASSES)) {
+                hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
     mg_server_destroy(S.release());
     return bad(MG_ERR_DEVICE, "server initialisation failed");
   }
-  S->tick_cap = 256;
-  if (!S->tick.grow(S->tick_cap * S->n_classes) || !capture_tick_graph(S.get())) {
-    mg_server_destroy(S.release());
-    return bad(MG_ERR_DEVICE, "tick graph initialisation failed");
+  S->free_entries.resize(S->n_classes);
+  S->hw.assign(S->n_classes, 0);
+  S->list_cap = 1024;
+  {
+    std::vector<ServeTickItem> z(S->list_cap * S->n_classes);
+    std::memset(z.data(), 0, z.size() * sizeof(ServeTickItem));
+    if (hipMalloc(&S->list_d, z.size() * sizeof(ServeTickItem)) != hipSuccess ||
+        hipMemcpy(S->list_d, z.data(), z.size() * sizeof(ServeTickItem),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      mg_server_destroy(S.release());
+      return bad(MG_ERR_DEVICE, "tick list allocation failed");
+    }
   }
+  for (auto& sl : S->slots) {
+    if (!sl.hdr.grow(1) || hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
+        !capture_tick_graph(S.get(), sl)) {
+      (void)hipGetLastError();
+      mg_server_destroy(S.release());
+      return bad(MG_ERR_DEVICE, "tick slot initialisation failed");
+    }
+  }
+  S->deliver_thr = std::thread(deliverer, S.get());
   S->thr = std::thread(scheduler, S.get());
   *out = S.release();
   return MG_OK;
+}
+
+// Page layout of a request (independent of which pages it gets): pages per class
+// in class order, each page's lanes take that class's envs in request order.
+static void layout_pages(Request* r, int n_classes) {
+  r->page_cls.clear();
+  r->cols.assign((size_t)PagePool::pages_for(r->per_class) * kPageEnvs, -1);
+  size_t p = 0;
+  for (int c = 0; c < n_classes; ++c) {
+    if (r->per_class[c] == 0) continue;
+    int lane = 0;
+    r->page_cls.push_back(c);
+    for (int64_t e = 0; e < r->n; ++e) {
+      if (r->cls[e] != c) continue;
+      if (lane == kPageEnvs) {
+        lane = 0;
+        ++p;
+        r->page_cls.push_back(c);
+      }
+      r->cols[p * kPageEnvs + lane++] = (int32_t)e;
+    }
+    ++p;
+  }
 }
 
 mg_status mg_server_submit(mg_server* S, const mg_request* req, uint64_t* ticket) {
@@ -557,6 +756,7 @@ mg_status mg_server_submit(mg_server* S, const mg_request* req, uint64_t* ticket
   const uint64_t now = clock_ns();
   r->arrival = (req->arrival_ns && req->arrival_ns < now) ? req->arrival_ns : now;
   const int64_t need = PagePool::pages_for(r->per_class);
+  if (need <= S->pool->cap_pages()) layout_pages(r.get(), S->n_classes);
   {
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->broken) return MG_ERR_DEVICE;
@@ -605,6 +805,11 @@ mg_status mg_server_get_stats(const mg_server* S, mg_server_stats* out) {
   out->queued = S->queued.load();
   out->cap_pages = S->pool ? S->pool->cap_pages() : 0;
   out->created_pages = S->pool ? S->pool->created_pages() : 0;
+  out->issue_ns = S->issue_ns.load();
+  out->wait_ns = S->wait_ns.load();
+  const int64_t na = S->admitted_n.load();
+  out->mean_queue_ns = na ? S->queue_ns.load() / na : 0;
+  out->max_queue_ns = S->max_queue_ns.load();
   return S->broken ? MG_ERR_DEVICE : MG_OK;
 }
 
@@ -616,15 +821,29 @@ void mg_server_destroy(mg_server* S) {
   }
   S->cv_sched.notify_all();
   if (S->thr.joinable()) S->thr.join();
+  {
+    std::lock_guard<std::mutex> lk(S->dmu);
+    S->deliver_stop = true;
+  }
+  S->dcv.notify_all();
+  if (S->deliver_thr.joinable()) S->deliver_thr.join();
   (void)hipSetDevice(S->device);
   if (S->stream) (void)hipStreamSynchronize(S->stream);
-  if (S->graph) (void)hipGraphExecDestroy(S->graph);
-  S->init.release();
-  S->cols_stage.release();
-  S->tick.release();
-  S->counts.release();
-  S->gather.release();
-  S->out.release();
+  for (auto& sl : S->slots) {
+    if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    sl.init.release();
+    sl.cols_stage.release();
+    sl.hdr.release();
+    sl.pre.release();
+    sl.post.release();
+    sl.gather.release();
+  }
+  for (Mirror<float>* m : S->out_all) {
+    m->release();
+    delete m;
+  }
+  if (S->list_d) (void)hipFree(S->list_d);
   for (float* b : S->slab_blocks) (void)hipFree(b);
   for (int32_t* c : S->slab_cols) (void)hipFree(c);
   if (S->nominal_dev) (void)hipFree(S->nominal_dev);

@@ -70,7 +70,8 @@ class MgRequest(ctypes.Structure):
 class MgServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("completed", "rejected", "ticks", "env_steps", "active_envs", "max_active_envs",
-                 "queued", "cap_pages", "created_pages")]
+                 "queued", "cap_pages", "created_pages", "issue_ns", "wait_ns", "mean_queue_ns",
+                 "max_queue_ns")]
 
 
 _vp = ctypes.c_void_p

@@ -111,8 +111,10 @@ def test_c2_trajectory_on_env_subset(mgmod, oracle):
 
 
 def test_fused_plain_graph_agree(mgmod):
-    """One fused launch of n_ctrl x S sub-steps, per-control-step graph launches and the plain
-    per-sub-step kernel give the same states (bitwise) and statistics."""
+    """One fused launch of n_ctrl x S sub-steps and per-control-step graph launches give the
+    same states and statistics bitwise; the plain per-sub-step kernel (eager or graph) agrees
+    bitwise with itself and with the fused kernel to rounding (it re-forms the lag wrench from
+    the stored thrust every sub-step instead of carrying it)."""
     E, T = 3000, 40
     classes = [LAGGED["bluerov2"], LAGGED["heavy"]]
     cls = env_classes(E, "halves")
@@ -126,9 +128,12 @@ def test_fused_plain_graph_agree(mgmod):
         say("mode", mode)
         res[mode] = _run(mgmod, classes, x0, act, 0.005, 4, env_class=cls, mult=mult,
                          targets=tgt, mode=mode)
-    for mode in ["plain", "graph", "graph_plain"]:
-        np.testing.assert_array_equal(res[mode][0], res["fused"][0])
-        np.testing.assert_array_equal(res[mode][1], res["fused"][1])
+    np.testing.assert_array_equal(res["graph"][0], res["fused"][0])
+    np.testing.assert_array_equal(res["graph"][1], res["fused"][1])
+    np.testing.assert_array_equal(res["graph_plain"][0], res["plain"][0])
+    np.testing.assert_array_equal(res["graph_plain"][1], res["plain"][1])
+    assert rel_err(res["plain"][0], res["fused"][0]) <= 1e-5
+    np.testing.assert_allclose(res["plain"][1], res["fused"][1], rtol=1e-5)
 
 
 def test_interleaved_classes_match_contiguous(mgmod, oracle):
@@ -282,40 +287,117 @@ def test_graph_replays_match_eager(mgmod):
     sim.close()
 
 
+def _env_err(x_gpu, x_ref):
+    """Per-env error in the norm of rel_err: max over components of |x - x_ref| / max(1, |x_ref|)."""
+    x_gpu = np.asarray(x_gpu, np.float64)
+    x_ref = np.asarray(x_ref, np.float64)
+    return np.max(np.abs(x_gpu - x_ref) / np.maximum(1.0, np.abs(x_ref)), axis=0)
+
+
+def _local_errors(oracle, classes, path, act, S, dt, cls, mult):
+    """Local parity along a path: path [T+1][D][n] holds x0 and the states after each
+    control step; the oracle advances every stored state by one control step (all T of them
+    in one batch) and the result is compared with the next stored state.  Returns the
+    per-env maximum over the T steps."""
+    T1, D, n = path.shape
+    T = T1 - 1
+    starts = np.ascontiguousarray(path[:T].transpose(1, 0, 2).reshape(D, T * n))
+    a = np.ascontiguousarray(act.transpose(1, 0, 2).reshape(1, act.shape[1], T * n))
+    ref = oracle.rollout(classes, starts, a, S, dt, env_class=np.tile(cls, T),
+                         mult=np.tile(mult, (1, T)))["x"]
+    nxt = path[1:].transpose(1, 0, 2).reshape(D, T * n)
+    return _env_err(nxt, ref).reshape(T, n).max(axis=0)
+
+
+def _oracle_spread(oracle, classes, x0, act, S, dt, cls, mult, members=3, eta=1e-6, seed=7):
+    """Conditioning of each env's trajectory: the FP64 oracle is run once clean and `members`
+    times with a random perturbation of relative size eta (about ten times the FP32 path's
+    typical one-step error) added to the state after every control step.  Returns the clean
+    final state and, per env, the largest final deviation of a perturbed run from the clean
+    one: how far local errors of that size carry the end state."""
+    D, n = x0.shape
+    rng = np.random.default_rng(seed)
+    x = np.tile(np.asarray(x0, np.float64), (1, members + 1))
+    ec, mm = np.tile(cls, members + 1), np.tile(mult, (1, members + 1))
+    for t in range(act.shape[0]):
+        x = oracle.rollout(classes, x, np.tile(act[t:t + 1], (1, 1, members + 1)), S, dt,
+                           env_class=ec, mult=mm)["x"]
+        noise = eta * rng.standard_normal((D, members * n)) * np.maximum(1.0, np.abs(x[:, n:]))
+        x[:, n:] += noise
+    clean = x[:, :n]
+    spread = np.max([_env_err(x[:, (k + 1) * n:(k + 2) * n], clean) for k in range(members)],
+                    axis=0)
+    return clean, spread
+
+
 @pytest.mark.slow
 def test_c3_full_size_sampled(mgmod, oracle):
-    """2^20 mixed envs, 16 sub-steps per launch, 200 launches from a graph: sampled envs
-    against the oracle, every env finite with a unit quaternion, plain kernel identical."""
+    """2^20 mixed envs, 16 sub-steps per launch, 200 launches from a graph, fused and plain.
+
+    Every env stays finite with a unit quaternion.  On a sample (every 1024th env plus the
+    envs where fused and plain end furthest apart) both paths are checked locally: each of
+    the 200 control steps, restarted in the oracle from the path's own state, agrees to the
+    one-step tolerance.  Over the whole horizon a few Heavy envs per 10^4 are ill-conditioned
+    (random throttles drive them through the inverted attitude, where the CG-below-CB
+    restoring moment is unstable): there the FP64 oracle itself moves by more than 1e-3 under
+    perturbations of the size of FP32 rounding, so no FP32 path can match it to 1e-3.  The
+    trajectory tolerance is asserted on the sampled envs whose oracle trajectory is
+    well-conditioned (random perturbations of 1e-6 after every control step move the end state
+    by at most the trajectory tolerance), which must be nearly all of them; on this workload
+    the ill-conditioned envs move by 0.07 to 0.8 under those perturbations, the
+    well-conditioned ones by 7e-5 at the median."""
     c = CONFIGS["c3"]
-    E = c.n_envs
+    E, T, S = c.n_envs, c.n_ctrl, c.substeps
     classes = [LAGGED["bluerov2"], LAGGED["heavy"]]
     cls = env_classes(E, "halves")
     x0 = initial_state(E, 21, c.seed_base + 2)
     x0[19:, cls == 0] = 0
     mult = param_multipliers(E, c.rho, c.seed_base + 1)
-    sample = np.unique(np.concatenate([np.arange(0, E, 1024), [0, E // 2 - 1, E // 2, E - 1]]))
     say("c3 generate actions")
-    act = torch.empty((c.n_ctrl, 8, E), dtype=torch.float32, device="cuda")
-    act_s = np.empty((c.n_ctrl, 8, len(sample)), np.float32)
-    for t, fr in enumerate(action_frames(c.n_ctrl, 8, E, c.seed_base + 3)):
+    frames = list(action_frames(T, 8, E, c.seed_base + 3))
+    act = torch.empty((T, 8, E), dtype=torch.float32, device="cuda")
+    for t, fr in enumerate(frames):
         act[t].copy_(torch.from_numpy(fr))
-        act_s[t] = fr[:, sample]
-    say("c3 fused graph rollout")
-    sim = mgmod.Sim(classes, E, c.dt_sub, c.substeps, env_class=cls)
-    sim.reset(state=dev(x0), param_mult=dev(mult))
-    stats = torch.empty((c.n_ctrl, 4), dtype=torch.float64, device="cuda")
-    sim.rollout(act, stats=stats)
-    xf = host(sim.get_state())
-    say("c3 plain graph rollout")
-    sim.reset(state=dev(x0), param_mult=dev(mult))
-    sim.rollout(act, plain=True)
-    xp = host(sim.get_state())
+    sim = mgmod.Sim(classes, E, c.dt_sub, S, env_class=cls)
+    final, trajs = {}, {}
+    stats = torch.empty((T, 4), dtype=torch.float64, device="cuda")
+    for mode in ("fused", "plain"):
+        say(f"c3 {mode} graph rollout with trajectory")
+        traj = torch.empty((T, 21, E), dtype=torch.float32, device="cuda")
+        sim.reset(state=dev(x0), param_mult=dev(mult))
+        sim.rollout(act, traj=traj, stats=stats if mode == "fused" else None,
+                    plain=(mode == "plain"))
+        final[mode] = host(sim.get_state())
+        trajs[mode] = traj
     st = host(stats)
     sim.close()
     del act
-    np.testing.assert_array_equal(xp, xf)
-    assert np.isfinite(xf).all() and np.all(st[:, 3] == 0)
+    xf, xp = final["fused"], final["plain"]
+    assert np.isfinite(xf).all() and np.isfinite(xp).all() and np.all(st[:, 3] == 0)
     np.testing.assert_allclose(np.linalg.norm(xf[3:7], axis=0), 1.0, atol=1e-6)
-    ref = oracle.rollout(classes, x0[:, sample], act_s, c.substeps, c.dt_sub,
-                         env_class=cls[sample], mult=mult[:, sample])
-    assert rel_err(xf[:, sample], ref["x"]) <= TOL_TRAJ
+    np.testing.assert_array_equal(host(trajs["fused"][-1]), xf)
+
+    d = _env_err(xp, xf)
+    regular = np.arange(0, E, 1024)
+    worst = np.argsort(-d)[:8]
+    sample = np.unique(np.concatenate([regular, [0, E // 2 - 1, E // 2, E - 1], worst]))
+    say(f"c3 fused vs plain at the end: max {d.max():.2e}, envs above 1e-3: {(d > 1e-3).sum()}")
+    idx = torch.from_numpy(sample).cuda()
+    act_s = np.stack([fr[:, sample] for fr in frames])
+    cs, ms = cls[sample], mult[:, sample]
+    for mode in ("fused", "plain"):
+        path = np.concatenate([x0[None, :, sample],
+                               host(trajs[mode].index_select(2, idx))], axis=0)
+        trajs[mode] = None
+        loc = _local_errors(oracle, classes, path, act_s, S, c.dt_sub, cs, ms)
+        say(f"c3 {mode}: worst local one-step error {loc.max():.2e}")
+        assert loc.max() <= TOL_ONE_STEP
+    say("c3 oracle conditioning on the sample")
+    clean, spread = _oracle_spread(oracle, classes, x0[:, sample], act_s, S, c.dt_sub, cs, ms)
+    well = spread <= TOL_TRAJ
+    in_regular = np.isin(sample, regular)
+    say(f"c3 well-conditioned: {well[in_regular].sum()} of {in_regular.sum()} regular samples, "
+        f"{well[np.isin(sample, worst)].sum()} of {len(worst)} most divergent envs")
+    assert well[in_regular].mean() >= 0.98
+    for x in (xf, xp):
+        assert _env_err(x[:, sample[well]], clean[:, well]).max() <= TOL_TRAJ

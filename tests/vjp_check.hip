@@ -84,7 +84,9 @@ double control_step_dot(const ClassConst& cc, const EnvConstT<double>& P, const 
   for (int i = 0; i < D; ++i) x[i] = x0[i];
   thrust_command<N>(cc, a, fcmd);
   command_wrench<N>(cc, fcmd, gcmd);
-  for (int s = 0; s < S; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, make_step_const_host(cc, dt));
+  double dg[6] = {0, 0, 0, 0, 0, 0};
+  if (LAG) lag_wrench<N>(cc, x, fcmd, dg);
+  for (int s = 0; s < S; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, make_step_const_host(cc, dt));
   double d = 0;
   for (int i = 0; i < D; ++i) d += lam[i] * x[i];
   return d;
@@ -120,9 +122,11 @@ void check_case(unsigned seed, int map, int S, double dt) {
   for (int i = 0; i < D; ++i) x[i] = x0[i];
   thrust_command<N>(cc, a, fcmd);
   command_wrench<N>(cc, fcmd, gcmd);
+  double dg[6] = {0, 0, 0, 0, 0, 0};
+  if (LAG) lag_wrench<N>(cc, x, fcmd, dg);
   for (int s = 0; s < S; ++s) {
     for (int i = 0; i < D; ++i) xs[s][i] = x[i];
-    rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, make_step_const_host(cc, dt));
+    rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, make_step_const_host(cc, dt));
   }
   double lam[D], fcb[N] = {0}, gcb[6] = {0}, ab[N];
   for (int i = 0; i < D; ++i) lam[i] = lam_out[i];

@@ -155,8 +155,11 @@ mg_status mg_set_state(mg_sim* sim, const float* state);
  *            two-pass reduction).  Or NULL. */
 mg_status mg_step(mg_sim* sim, const float* actions, int32_t n_ctrl, const float* targets,
                   float* traj, double* stats);
-/* Same result as mg_step, computed by the plain kernel: one launch per RK4
- * sub-step per class, state round-tripping HBM between launches. */
+/* The same discrete map as mg_step, computed by the plain kernel: one launch
+ * per RK4 sub-step per class, state round-tripping HBM between launches.  The
+ * thruster lag states advance by the one-sub-step lag factor per launch
+ * instead of its S-th power once per control step, so results agree with
+ * mg_step to rounding, not bitwise. */
 mg_status mg_step_plain(mg_sim* sim, const float* actions, int32_t n_ctrl, const float* targets,
                         float* traj, double* stats);
 /* T control steps as T launches per class (plain != 0: T * substeps

@@ -34,8 +34,8 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src, extra=()):
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
+def _compile(src, extra=(), build_dir=BUILD):
+    obj = os.path.join(build_dir, os.path.basename(src)[:-4] + ".o")
     cmd = [_hipcc(), "-c", *CFLAGS, *extra, src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -45,14 +45,12 @@ def _compile(src, extra=()):
 
 def build(verbose=True, out=None, build_dir=None, defines=()):
     """Compile and link; `out`/`build_dir`/`defines` allow side builds of tuning variants."""
-    global BUILD
-    if build_dir:
-        BUILD = build_dir
-    os.makedirs(BUILD, exist_ok=True)
+    bdir = build_dir or BUILD
+    os.makedirs(bdir, exist_ok=True)
     extra = [f"-D{d}" for d in defines]
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda f: _compile(f, extra), srcs))
+        objs = list(ex.map(lambda f: _compile(f, extra, bdir), srcs))
     lib = out or LIB
     tmp = lib + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]

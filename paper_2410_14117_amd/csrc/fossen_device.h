@@ -20,7 +20,10 @@ __host__ __device__ inline float fma_t(float a, float b, float c) { return fmaf(
 __host__ __device__ inline double fma_t(double a, double b, double c) { return fma(a, b, c); }
 __host__ __device__ inline float abs_t(float a) { return fabsf(a); }
 __host__ __device__ inline double abs_t(double a) { return fabs(a); }
-__device__ inline float rsqrt_t(float a) { return rsqrtf(a); }
+// Used only for 1/|q| with |q|^2 close to 1 (never denormal): the hardware
+// reciprocal square root (v_rsq_f32, 1 ulp) without the denormal rescaling
+// rsqrtf wraps around it, which gives the same value for normal inputs.
+__device__ inline float rsqrt_t(float a) { return __builtin_amdgcn_rsqf(a); }
 __host__ __device__ inline double rsqrt_t(double a) { return 1.0 / sqrt(a); }
 
 // Per-env constants held in registers for the whole launch.
@@ -230,10 +233,13 @@ __host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvCo
 // f_cmd + sigma_i (f - f_cmd) exactly (class constants), the stage wrenches
 // are B f_cmd + sigma_i dg with dg = B (f - f_cmd), and the sub-step maps
 // f - f_cmd and dg alike to rho times themselves: the same discrete map as
-// generic RK4 on the lag states.  dg is carried from sub-step to sub-step of
-// a control step (formed once per control step by lag_wrench), so no
-// allocation product is needed inside the sub-step.  Without a lag the wrench
-// is the command wrench B f_cmd throughout.
+// generic RK4 on the lag states.  Over the S sub-steps of a control step
+// f - f_cmd therefore shrinks by rho^S and dg by rho per sub-step, so
+// begin_control_step forms dg once and sets the lag states to their
+// end-of-control-step value f_cmd + rho^S (f - f_cmd) directly; the sub-step
+// then touches neither the lag states nor the allocation matrix, only
+// dg <- rho dg.  Without a lag the wrench is the command wrench B f_cmd
+// throughout.
 template <int N, class T>
 __host__ __device__ __forceinline__ void lag_wrench(const ClassConst& cc, const T* x,
                                                     const T (&fcmd)[N], T (&dg)[6]) {
@@ -246,9 +252,25 @@ __host__ __device__ __forceinline__ void lag_wrench(const ClassConst& cc, const 
   }
 }
 
+// Start of a control step with the commanded thrust f_cmd: dg = B (f - f_cmd)
+// and f <- f_cmd + rho_s (f - f_cmd), rho_s = rho^S for the S sub-steps that
+// follow (rho itself when one sub-step follows).
+template <int N, bool LAG, class T>
+__host__ __device__ __forceinline__ void begin_control_step(const ClassConst& cc, T* x,
+                                                            const T (&fcmd)[N], T (&dg)[6],
+                                                            T rho_s) {
+  if constexpr (LAG) {
+    lag_wrench<N>(cc, x, fcmd, dg);
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[13 + i] = fma_t(rho_s, x[13 + i] - fcmd[i], fcmd[i]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dg[k] = T(0);
+  }
+}
+
 template <int N, bool LAG, class T>
 __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P,
-                                                     const ClassConst& cc, const T (&fcmd)[N],
                                                      const T (&gcmd)[6], T (&dg)[6],
                                                      const StepConstT<T>& sc) {
   T tau[6];
@@ -299,8 +321,6 @@ __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P
   for (int i = 0; i < 13; ++i) x[i] = fma_t(f6(i), acc[i] + k[i], x[i]);
   if constexpr (LAG) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[13 + i] = fma_t(sc.rho, x[13 + i] - fcmd[i], fcmd[i]);
-#pragma unroll
     for (int k = 0; k < 6; ++k) dg[k] *= sc.rho;
   }
   const T n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
@@ -309,6 +329,24 @@ __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P
   x[4] *= inv;
   x[5] *= inv;
   x[6] *= inv;
+}
+
+// One control step: S sub-steps with the commanded thrust f_cmd (wrench gcmd)
+// held; rho_s = rho^S.  MG_SUBSTEP_UNROLL sub-steps are unrolled per loop trip.
+#ifndef MG_SUBSTEP_UNROLL
+#define MG_SUBSTEP_UNROLL 1
+#endif
+#define MG_PRAGMA_(x) _Pragma(#x)
+#define MG_UNROLL_(n) MG_PRAGMA_(unroll n)
+template <int N, bool LAG, class T>
+__host__ __device__ __forceinline__ void control_step(T* x, const EnvConstT<T>& P,
+                                                      const ClassConst& cc, const T (&fcmd)[N],
+                                                      const T (&gcmd)[6], const StepConstT<T>& sc,
+                                                      int S, T rho_s) {
+  T dg[6];
+  begin_control_step<N, LAG>(cc, x, fcmd, dg, rho_s);
+  MG_UNROLL_(MG_SUBSTEP_UNROLL)
+  for (int s = 0; s < S; ++s) rk4_substep<N, LAG>(x, P, gcmd, dg, sc);
 }
 
 }  // namespace mg

@@ -42,10 +42,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const Class
       for (int i = 0; i < D; ++i) ck[i * a.E] = x[i];
       for (int i = D; i < a.D; ++i) ck[i * a.E] = 0.0f;
     }
-    float act[N], fcmd[N], gcmd[6], dg[6];
+    float act[N], fcmd[N], gcmd[6];
     load_command<N>(cc, a, t, c, act, fcmd, gcmd);
-    if constexpr (LAG) lag_wrench<N>(cc, x, fcmd, dg);
-    for (int s = 0; s < a.substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, sc);
+    control_step<N, LAG>(x, P, cc, fcmd, gcmd, sc, a.substeps, cc.rho_s);
     if (a.traj) {
       float* tf = a.traj + (int64_t)t * a.D * a.E + c;
 #pragma unroll
@@ -80,15 +79,29 @@ __global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const Class
     const float* ck = a.ckpt + (int64_t)seg * a.D * a.E + c;
 #pragma unroll
     for (int i = 0; i < D; ++i) x[i] = ck[i * a.E];
+    // (the forward sets the lag states to their end-of-control-step value at
+    // the start; the sub-step inputs the VJP linearises about carry the lag
+    // states of each sub-step, f_cmd + rho^s (f - f_cmd), kept here in fs)
     for (int t = t0; t < t1; ++t) {
-      float act[N], fcmd[N], gcmd[6], dg[6];
+      float act[N], fcmd[N], gcmd[6], dg[6], fs[LAG ? N : 1];
       load_command<N>(cc, a, t, c, act, fcmd, gcmd);
-      if constexpr (LAG) lag_wrench<N>(cc, x, fcmd, dg);
+      if constexpr (LAG) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) fs[i] = x[13 + i];
+      }
+      begin_control_step<N, LAG>(cc, x, fcmd, dg, cc.rho_s);
       for (int s = 0; s < S; ++s) {
         float* sb = a.segbuf + (int64_t)((t - t0) * S + s) * D * a.Ep + j;
 #pragma unroll
-        for (int i = 0; i < D; ++i) sb[i * a.Ep] = x[i];
-        rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, sc);
+        for (int i = 0; i < 13; ++i) sb[i * a.Ep] = x[i];
+        if constexpr (LAG) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            sb[(13 + i) * a.Ep] = fs[i];
+            fs[i] = fma_t(sc.rho, fs[i] - fcmd[i], fcmd[i]);
+          }
+        }
+        rk4_substep<N, LAG>(x, P, gcmd, dg, sc);
       }
     }
     // reverse sweep over the segment

@@ -61,9 +61,9 @@ __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickItem* __re
     for (int i = 0; i < N; ++i) act[i] = af[i * it.ld];
     thrust_command<N>(cc, act, fcmd);
     command_wrench<N>(cc, fcmd, gcmd);
-    float dg[6];
-    if constexpr (LAG) lag_wrench<N>(cc, x, fcmd, dg);
-    for (int s = 0; s < substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, sc);
+    // substeps is the server's S (cc.rho_s = rho^S) or, for the FIFO plain
+    // baseline, 1 (rho)
+    control_step<N, LAG>(x, P, cc, fcmd, gcmd, sc, substeps, substeps == 1 ? cc.rho : cc.rho_s);
 #pragma unroll
     for (int i = 0; i < D; ++i) it.block[i * kPageEnvs + lane] = x[i];
   }

@@ -79,9 +79,7 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
       for (int i = 0; i < N; ++i) act[i] = af[i * a.E];
       thrust_command<N>(cc, act, fcmd);
       command_wrench<N>(cc, fcmd, gcmd);
-      float dg[6];
-      if constexpr (LAG) lag_wrench<N>(cc, x, fcmd, dg);
-      for (int s = 0; s < substeps; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, sc);
+      control_step<N, LAG>(x, P, cc, fcmd, gcmd, sc, substeps, PLAIN ? cc.rho : cc.rho_s);
       if (a.traj) {
         float* tf = a.traj + (int64_t)t * a.D * a.E + c;
 #pragma unroll

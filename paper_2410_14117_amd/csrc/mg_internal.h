@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "mg.h"
+
 namespace mg {
 
 constexpr int kMaxThr = 8;
@@ -44,8 +46,13 @@ struct ClassConst {
   int32_t n_thr;
   int32_t thr_map;       // 0 linear, 1 quadratic
   int32_t lag;
-  int32_t pad_;
+  float rho_s;           // rho^S for the owner's S sub-steps per control step
 };
+
+// Class constants for sub-steps of dt, S sub-steps per control step.  The
+// allocation matrix is formed from the thruster geometry: column i is
+// [d_i ; r_i x d_i].
+ClassConst make_class_const(const mg_vehicle& v, double dt, int substeps);
 
 // Nominal parameters of a class for the reset kernel (device table).
 struct ClassNominal {

@@ -67,6 +67,32 @@ struct mg_sim {
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
+// Class constants the step kernels read from scalar registers.
+ClassConst mg::make_class_const(const mg_vehicle& v, double dt, int substeps) {
+  ClassConst c;
+  std::memset(&c, 0, sizeof(c));
+  for (int i = 0; i < v.n_thr; ++i) {
+    const double* r = v.thr_pos[i];
+    const double* d = v.thr_dir[i];
+    const double col[6] = {d[0], d[1], d[2], r[1] * d[2] - r[2] * d[1],
+                           r[2] * d[0] - r[0] * d[2], r[0] * d[1] - r[1] * d[0]};
+    for (int k = 0; k < 6; ++k) c.B[k][i] = (float)col[k];
+  }
+  c.f_max = (float)v.f_max;
+  c.inv_tau = v.thr_tau > 0.0 ? (float)(1.0 / v.thr_tau) : 0.0f;
+  const double z = v.thr_tau > 0.0 ? dt / v.thr_tau : 0.0;
+  const double rho = 1.0 - z + z * z / 2 - z * z * z / 6 + z * z * z * z / 24;
+  c.sigma2 = (float)(1.0 - z / 2);
+  c.sigma3 = (float)(1.0 - z / 2 + z * z / 4);
+  c.sigma4 = (float)(1.0 - z + z * z / 2 - z * z * z / 4);
+  c.rho = (float)rho;
+  c.rho_s = (float)std::pow(rho, (double)substeps);
+  c.n_thr = v.n_thr;
+  c.thr_map = v.thr_map;
+  c.lag = v.thr_tau > 0.0 ? 1 : 0;
+  return c;
+}
+
 namespace {
 
 mg_status fail(mg_sim* s, mg_status code, const std::string& msg) {
@@ -109,32 +135,6 @@ mg_status check_usable(mg_sim* s) {
 void clear_graphs(mg_sim* s) {
   for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
   s->graphs.clear();
-}
-
-// Class constants the step kernels read from scalar registers.  The
-// allocation matrix is formed here from the thruster geometry: column i is
-// [d_i ; r_i x d_i].
-ClassConst make_class_const(const mg_vehicle& v, double dt) {
-  ClassConst c;
-  std::memset(&c, 0, sizeof(c));
-  for (int i = 0; i < v.n_thr; ++i) {
-    const double* r = v.thr_pos[i];
-    const double* d = v.thr_dir[i];
-    const double col[6] = {d[0], d[1], d[2], r[1] * d[2] - r[2] * d[1],
-                           r[2] * d[0] - r[0] * d[2], r[0] * d[1] - r[1] * d[0]};
-    for (int k = 0; k < 6; ++k) c.B[k][i] = (float)col[k];
-  }
-  c.f_max = (float)v.f_max;
-  c.inv_tau = v.thr_tau > 0.0 ? (float)(1.0 / v.thr_tau) : 0.0f;
-  const double z = v.thr_tau > 0.0 ? dt / v.thr_tau : 0.0;
-  c.sigma2 = (float)(1.0 - z / 2);
-  c.sigma3 = (float)(1.0 - z / 2 + z * z / 4);
-  c.sigma4 = (float)(1.0 - z + z * z / 2 - z * z * z / 4);
-  c.rho = (float)(1.0 - z + z * z / 2 - z * z * z / 6 + z * z * z * z / 24);
-  c.n_thr = v.n_thr;
-  c.thr_map = v.thr_map;
-  c.lag = v.thr_tau > 0.0 ? 1 : 0;
-  return c;
 }
 
 ClassNominal make_nominal(const mg_vehicle& v) {
@@ -417,7 +417,7 @@ mg_status mg_create(const mg_config* cfg, mg_sim** out) {
   int32_t dmax = 13, nmax = 1;
   for (int k = 0; k < cfg->n_classes; ++k) {
     const mg_vehicle& v = cfg->classes[k];
-    s->cc.push_back(make_class_const(v, cfg->dt_sub));
+    s->cc.push_back(make_class_const(v, cfg->dt_sub, cfg->substeps));
     s->nominal.push_back(make_nominal(v));
     nmax = std::max(nmax, v.n_thr);
     if (v.thr_tau > 0.0) dmax = std::max(dmax, 13 + v.n_thr);

@@ -190,29 +190,6 @@ bool fail_server(mg_server* S, const std::string& msg) {
     if (e_ != hipSuccess) return fail_server(S, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-ClassConst class_const(const mg_vehicle& v, double dt) {
-  ClassConst c;
-  std::memset(&c, 0, sizeof(c));
-  for (int i = 0; i < v.n_thr; ++i) {
-    const double* r = v.thr_pos[i];
-    const double* d = v.thr_dir[i];
-    const double col[6] = {d[0], d[1], d[2], r[1] * d[2] - r[2] * d[1],
-                           r[2] * d[0] - r[0] * d[2], r[0] * d[1] - r[1] * d[0]};
-    for (int k = 0; k < 6; ++k) c.B[k][i] = (float)col[k];
-  }
-  c.f_max = (float)v.f_max;
-  c.inv_tau = v.thr_tau > 0.0 ? (float)(1.0 / v.thr_tau) : 0.0f;
-  const double z = v.thr_tau > 0.0 ? dt / v.thr_tau : 0.0;
-  c.sigma2 = (float)(1.0 - z / 2);
-  c.sigma3 = (float)(1.0 - z / 2 + z * z / 4);
-  c.sigma4 = (float)(1.0 - z + z * z / 2 - z * z * z / 4);
-  c.rho = (float)(1.0 - z + z * z / 2 - z * z * z / 6 + z * z * z * z / 24);
-  c.n_thr = v.n_thr;
-  c.thr_map = v.thr_map;
-  c.lag = v.thr_tau > 0.0 ? 1 : 0;
-  return c;
-}
-
 ClassNominal class_nominal(const mg_vehicle& v) {
   ClassNominal n;
   std::memset(&n, 0, sizeof(n));
@@ -641,7 +618,7 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   S->max_queue = cfg->max_queue > 0 ? cfg->max_queue : 65536;
   for (int k = 0; k < cfg->n_classes; ++k) {
     const mg_vehicle& v = cfg->classes[k];
-    S->cc.push_back(class_const(v, cfg->dt_sub));
+    S->cc.push_back(make_class_const(v, cfg->dt_sub, cfg->substeps));
     S->nominal.push_back(class_nominal(v));
     S->n_max = std::max(S->n_max, v.n_thr);
     if (v.thr_tau > 0.0) S->D = std::max(S->D, 13 + v.n_thr);

@@ -43,7 +43,7 @@ EnvConstT<double> make_env(const Theta& th, double zg, double zb) {
 }
 
 template <int N>
-ClassConst make_class(std::mt19937_64& g, bool lag, int map, double dt) {
+ClassConst make_class(std::mt19937_64& g, bool lag, int map, double dt, int S) {
   std::uniform_real_distribution<double> U(-1, 1);
   ClassConst c;
   std::memset(&c, 0, sizeof c);
@@ -57,6 +57,7 @@ ClassConst make_class(std::mt19937_64& g, bool lag, int map, double dt) {
   c.sigma3 = (float)(1 - z / 2 + z * z / 4);
   c.sigma4 = (float)(1 - z + z * z / 2 - z * z * z / 4);
   c.rho = (float)(1 - z + z * z / 2 - z * z * z / 6 + z * z * z * z / 24);
+  c.rho_s = (float)std::pow(1 - z + z * z / 2 - z * z * z / 6 + z * z * z * z / 24, (double)S);
   c.n_thr = N;
   c.thr_map = map;
   c.lag = lag;
@@ -84,9 +85,7 @@ double control_step_dot(const ClassConst& cc, const EnvConstT<double>& P, const 
   for (int i = 0; i < D; ++i) x[i] = x0[i];
   thrust_command<N>(cc, a, fcmd);
   command_wrench<N>(cc, fcmd, gcmd);
-  double dg[6] = {0, 0, 0, 0, 0, 0};
-  if (LAG) lag_wrench<N>(cc, x, fcmd, dg);
-  for (int s = 0; s < S; ++s) rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, make_step_const_host(cc, dt));
+  control_step<N, LAG>(x, P, cc, fcmd, gcmd, make_step_const_host(cc, dt), S, (double)cc.rho_s);
   double d = 0;
   for (int i = 0; i < D; ++i) d += lam[i] * x[i];
   return d;
@@ -97,7 +96,7 @@ void check_case(unsigned seed, int map, int S, double dt) {
   constexpr int D = Dims<N, LAG>::D;
   std::mt19937_64 g(seed);
   std::uniform_real_distribution<double> U(-1, 1);
-  const ClassConst cc = make_class<N>(g, LAG, map, dt);
+  const ClassConst cc = make_class<N>(g, LAG, map, dt, S);
   Theta th;
   const double nominal[23] = {11.5, 0.16, 0.16, 0.16, 5.5, 12.7, 14.6, 0.12, 0.12, 0.12,
                               4, 6, 5, 0.07, 0.07, 0.07, 18, 21, 37, 0.45, 0.45, 0.45,
@@ -117,16 +116,23 @@ void check_case(unsigned seed, int map, int S, double dt) {
   double lam_out[D];
   for (int i = 0; i < D; ++i) lam_out[i] = U(g);
 
-  // reverse mode through one control step: store the sub-step inputs, sweep back
-  double xs[64][D], x[D], fcmd[N], gcmd[6];
+  // reverse mode through one control step: store the sub-step inputs (with the
+  // lag states of each sub-step, f_cmd + rho^s (f - f_cmd)), sweep back
+  double xs[64][D], x[D], fcmd[N], gcmd[6], fs[N];
   for (int i = 0; i < D; ++i) x[i] = x0[i];
   thrust_command<N>(cc, a, fcmd);
   command_wrench<N>(cc, fcmd, gcmd);
-  double dg[6] = {0, 0, 0, 0, 0, 0};
-  if (LAG) lag_wrench<N>(cc, x, fcmd, dg);
+  for (int i = 0; i < N; ++i) fs[i] = LAG ? x[13 + i] : 0.0;
+  double dg[6];
+  begin_control_step<N, LAG>(cc, x, fcmd, dg, (double)cc.rho_s);
+  const StepConstT<double> sc = make_step_const_host(cc, dt);
   for (int s = 0; s < S; ++s) {
-    for (int i = 0; i < D; ++i) xs[s][i] = x[i];
-    rk4_substep<N, LAG>(x, P, cc, fcmd, gcmd, dg, make_step_const_host(cc, dt));
+    for (int i = 0; i < 13; ++i) xs[s][i] = x[i];
+    for (int i = 13; i < D; ++i) {
+      xs[s][i] = fs[i - 13];
+      fs[i - 13] = sc.rho * (fs[i - 13] - fcmd[i - 13]) + fcmd[i - 13];
+    }
+    rk4_substep<N, LAG>(x, P, gcmd, dg, sc);
   }
   double lam[D], fcb[N] = {0}, gcb[6] = {0}, ab[N];
   for (int i = 0; i < D; ++i) lam[i] = lam_out[i];

@@ -62,7 +62,7 @@ __device__ __forceinline__ EnvConst load_env_const(const float* __restrict__ der
 template <class T>
 struct StepConstT {
   T h2, h2q, dt, dtq, h6, h6q;   // stage / combination factors; *q: quaternion rows (x 1/2)
-  T two;
+  T two, third;
   T s2, s3, s4, rho;             // closed-form lag stage factors (ClassConst)
 };
 
@@ -82,6 +82,7 @@ __device__ __forceinline__ StepConstT<float> make_step_const(const ClassConst& c
   k.h6 = to_vgpr(h6);
   k.h6q = to_vgpr(0.5f * h6);
   k.two = to_vgpr(2.0f);
+  k.third = to_vgpr(1.0f / 3.0f);
   k.s2 = to_vgpr(cc.sigma2);
   k.s3 = to_vgpr(cc.sigma3);
   k.s4 = to_vgpr(cc.sigma4);
@@ -95,6 +96,7 @@ inline StepConstT<double> make_step_const_host(const ClassConst& cc, double dt) 
   const double h2 = 0.5 * dt, h6 = dt * (1.0 / 6.0);
   k.h2 = h2; k.h2q = 0.5 * h2; k.dt = dt; k.dtq = 0.5 * dt; k.h6 = h6; k.h6q = 0.5 * h6;
   k.two = 2.0;
+  k.third = 1.0 / 3.0;
   k.s2 = cc.sigma2; k.s3 = cc.sigma3; k.s4 = cc.sigma4; k.rho = cc.rho;
   return k;
 }
@@ -173,10 +175,11 @@ __host__ __device__ __forceinline__ void command_wrench(const ClassConst& cc, co
 //         C(nu) nu = [w x a ; v x a + w x b], [a; b] = M nu (Kirchhoff form of
 //         the skew-symmetric C_RB + C_A), D diagonal linear + quadratic,
 //         g = -[(W-B) k ; h x k], k = R(q)^T e3, h = (0, 0, W z_g - B z_b).
-// xd may not alias x.
+// rhs_residual writes the kinematic rows xd[0..6] and the residual
+// r = tau - C nu - D nu - g; rhs_core applies M^-1 to it.  xd may not alias x.
 template <class T>
-__host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvConstT<T>& P,
-                                                  const T (&tau)[6]) {
+__host__ __device__ __forceinline__ void rhs_residual(const T* x, T* xd, T (&res)[6],
+                                                      const EnvConstT<T>& P, const T (&tau)[6]) {
   const T qw = x[3], qx = x[4], qy = x[5], qz = x[6];
   const T u = x[7], v = x[8], w = x[9], p = x[10], q = x[11], r = x[12];
 
@@ -216,13 +219,63 @@ __host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvCo
   const T r4 = fma_t(-e4, q, fma_t(P.hz, k0,
                    fma_t(p, br, fma_t(-r, bp, fma_t(u, aw, fma_t(-w, au, tau[4]))))));
   const T r5 = fma_t(-e5, r, fma_t(q, bp, fma_t(-p, bq, fma_t(v, au, fma_t(-u, av, tau[5])))));
+  res[0] = r0; res[1] = r1; res[2] = r2; res[3] = r3; res[4] = r4; res[5] = r5;
+}
+
+template <class T>
+__host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvConstT<T>& P,
+                                                  const T (&tau)[6]) {
+  T r[6];
+  rhs_residual(x, xd, r, P, tau);
   // nu' = M^-1 r
-  xd[7] = fma_t(P.Iuq, r4, P.Iuu * r0);
-  xd[8] = fma_t(P.Ivp, r3, P.Ivv * r1);
-  xd[9] = P.Iww * r2;
-  xd[10] = fma_t(P.Ipp, r3, P.Ivp * r1);
-  xd[11] = fma_t(P.Iqq, r4, P.Iuq * r0);
-  xd[12] = P.Irr * r5;
+  xd[7] = fma_t(P.Iuq, r[4], P.Iuu * r[0]);
+  xd[8] = fma_t(P.Ivp, r[3], P.Ivv * r[1]);
+  xd[9] = P.Iww * r[2];
+  xd[10] = fma_t(P.Ipp, r[3], P.Ivp * r[1]);
+  xd[11] = fma_t(P.Iqq, r[4], P.Iuq * r[0]);
+  xd[12] = P.Irr * r[5];
+}
+
+// (h/2) M^-1 for the sub-step h: the structured inverse pre-scaled once per
+// launch, so the RK4 stage velocities come from the residuals in FMAs alone
+// (nu + (h/2) M^-1 r = nu + A r, nu + h M^-1 r = nu + 2 A r, and the
+// combination (h/6) M^-1 (r1 + 2 r2 + 2 r3 + r4) = (1/3) A (...), M^-1 being
+// constant over the sub-step).
+template <class T>
+struct HalfInvT {
+  T uu, vv, ww, pp, qq, rr, uq, vp;
+};
+
+template <class T>
+__host__ __device__ __forceinline__ HalfInvT<T> half_step_inverse(const EnvConstT<T>& P, T h2) {
+  HalfInvT<T> A;
+  A.uu = h2 * P.Iuu; A.vv = h2 * P.Ivv; A.ww = h2 * P.Iww; A.pp = h2 * P.Ipp;
+  A.qq = h2 * P.Iqq; A.rr = h2 * P.Irr; A.uq = h2 * P.Iuq; A.vp = h2 * P.Ivp;
+  return A;
+}
+
+// y = base + A r
+template <class T>
+__host__ __device__ __forceinline__ void add_inv(const HalfInvT<T>& A, const T (&r)[6],
+                                                 const T* base, T* y) {
+  y[0] = fma_t(A.uu, r[0], fma_t(A.uq, r[4], base[0]));
+  y[1] = fma_t(A.vv, r[1], fma_t(A.vp, r[3], base[1]));
+  y[2] = fma_t(A.ww, r[2], base[2]);
+  y[3] = fma_t(A.pp, r[3], fma_t(A.vp, r[1], base[3]));
+  y[4] = fma_t(A.qq, r[4], fma_t(A.uq, r[0], base[4]));
+  y[5] = fma_t(A.rr, r[5], base[5]);
+}
+
+// y = A r
+template <class T>
+__host__ __device__ __forceinline__ void mul_inv(const HalfInvT<T>& A, const T (&r)[6],
+                                                 T (&y)[6]) {
+  y[0] = fma_t(A.uu, r[0], A.uq * r[4]);
+  y[1] = fma_t(A.vv, r[1], A.vp * r[3]);
+  y[2] = A.ww * r[2];
+  y[3] = fma_t(A.pp, r[3], A.vp * r[1]);
+  y[4] = fma_t(A.qq, r[4], A.uq * r[0]);
+  y[5] = A.rr * r[5];
 }
 
 // One classical RK4 sub-step (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) of
@@ -271,8 +324,8 @@ __host__ __device__ __forceinline__ void begin_control_step(const ClassConst& cc
 
 template <int N, bool LAG, class T>
 __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P,
-                                                     const T (&gcmd)[6], T (&dg)[6],
-                                                     const StepConstT<T>& sc) {
+                                                     const HalfInvT<T>& A, const T (&gcmd)[6],
+                                                     T (&dg)[6], const StepConstT<T>& sc) {
   T tau[6];
   if constexpr (LAG) {
 #pragma unroll
@@ -281,47 +334,66 @@ __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P
 #pragma unroll
     for (int k = 0; k < 6; ++k) tau[k] = gcmd[k];
   }
-  // stage / combination factors per row; the quaternion rows of rhs_core are 2 q'
-  auto f2 = [&](int i) { return (i >= 3 && i < 7) ? sc.h2q : sc.h2; };
-  auto f1 = [&](int i) { return (i >= 3 && i < 7) ? sc.dtq : sc.dt; };
-  auto f6 = [&](int i) { return (i >= 3 && i < 7) ? sc.h6q : sc.h6; };
-  T k[13], X[13], acc[13];
-  rhs_core(x, k, P, tau);
+  // stage / combination factors of the kinematic rows; the quaternion rows of
+  // rhs_residual are 2 q'.  The velocity rows go through A = (h/2) M^-1.
+  auto f2 = [&](int i) { return (i >= 3) ? sc.h2q : sc.h2; };
+  auto f1 = [&](int i) { return (i >= 3) ? sc.dtq : sc.dt; };
+  auto f6 = [&](int i) { return (i >= 3) ? sc.h6q : sc.h6; };
+  // acc: kinematic rates (rows 0..6) and residuals (rows 7..12) summed with
+  // the RK4 weights 1, 2, 2, 1
+  T k[7], r[6], X[13], acc[13], t[6];
+  rhs_residual(x, k, r, P, tau);
 #pragma unroll
-  for (int i = 0; i < 13; ++i) {
+  for (int i = 0; i < 7; ++i) {
     acc[i] = k[i];
     X[i] = fma_t(f2(i), k[i], x[i]);
   }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[7 + i] = r[i];
+  add_inv(A, r, x + 7, X + 7);
   if constexpr (LAG) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s2, dg[j], gcmd[j]);
   }
-  rhs_core(X, k, P, tau);
+  rhs_residual(X, k, r, P, tau);
 #pragma unroll
-  for (int i = 0; i < 13; ++i) {
+  for (int i = 0; i < 7; ++i) {
     acc[i] = fma_t(sc.two, k[i], acc[i]);
     X[i] = fma_t(f2(i), k[i], x[i]);
   }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[7 + i] = fma_t(sc.two, r[i], acc[7 + i]);
+  add_inv(A, r, x + 7, X + 7);
   if constexpr (LAG) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s3, dg[j], gcmd[j]);
   }
-  rhs_core(X, k, P, tau);
+  rhs_residual(X, k, r, P, tau);
 #pragma unroll
-  for (int i = 0; i < 13; ++i) {
+  for (int i = 0; i < 7; ++i) {
     acc[i] = fma_t(sc.two, k[i], acc[i]);
     X[i] = fma_t(f1(i), k[i], x[i]);
   }
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[7 + i] = fma_t(sc.two, r[i], acc[7 + i]);
+  mul_inv(A, r, t);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) X[7 + i] = fma_t(sc.two, t[i], x[7 + i]);
   if constexpr (LAG) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s4, dg[j], gcmd[j]);
   }
-  rhs_core(X, k, P, tau);
+  rhs_residual(X, k, r, P, tau);
 #pragma unroll
-  for (int i = 0; i < 13; ++i) x[i] = fma_t(f6(i), acc[i] + k[i], x[i]);
+  for (int i = 0; i < 7; ++i) x[i] = fma_t(f6(i), acc[i] + k[i], x[i]);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) r[i] += acc[7 + i];
+  mul_inv(A, r, t);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) x[7 + i] = fma_t(sc.third, t[i], x[7 + i]);
   if constexpr (LAG) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) dg[k] *= sc.rho;
+    for (int k2 = 0; k2 < 6; ++k2) dg[k2] *= sc.rho;
   }
   const T n2 = x[3] * x[3] + x[4] * x[4] + x[5] * x[5] + x[6] * x[6];
   const T inv = rsqrt_t(n2);
@@ -340,13 +412,13 @@ __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P
 #define MG_UNROLL_(n) MG_PRAGMA_(unroll n)
 template <int N, bool LAG, class T>
 __host__ __device__ __forceinline__ void control_step(T* x, const EnvConstT<T>& P,
-                                                      const ClassConst& cc, const T (&fcmd)[N],
-                                                      const T (&gcmd)[6], const StepConstT<T>& sc,
-                                                      int S, T rho_s) {
+                                                      const HalfInvT<T>& A, const ClassConst& cc,
+                                                      const T (&fcmd)[N], const T (&gcmd)[6],
+                                                      const StepConstT<T>& sc, int S, T rho_s) {
   T dg[6];
   begin_control_step<N, LAG>(cc, x, fcmd, dg, rho_s);
   MG_UNROLL_(MG_SUBSTEP_UNROLL)
-  for (int s = 0; s < S; ++s) rk4_substep<N, LAG>(x, P, gcmd, dg, sc);
+  for (int s = 0; s < S; ++s) rk4_substep<N, LAG>(x, P, A, gcmd, dg, sc);
 }
 
 }  // namespace mg

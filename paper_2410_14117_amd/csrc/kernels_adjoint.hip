@@ -35,6 +35,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const Class
   for (int i = 0; i < D; ++i) x[i] = a.state[i * a.Ep + j];
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
   const StepConstT<float> sc = make_step_const(cc, a.dt);
+  const HalfInvT<float> A = half_step_inverse(P, sc.h2);
   for (int t = 0; t < a.T; ++t) {
     if (t % a.ckpt_every == 0) {
       float* ck = a.ckpt + (int64_t)(t / a.ckpt_every) * a.D * a.E + c;
@@ -44,7 +45,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const Class
     }
     float act[N], fcmd[N], gcmd[6];
     load_command<N>(cc, a, t, c, act, fcmd, gcmd);
-    control_step<N, LAG>(x, P, cc, fcmd, gcmd, sc, a.substeps, cc.rho_s);
+    control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, a.substeps, cc.rho_s);
     if (a.traj) {
       float* tf = a.traj + (int64_t)t * a.D * a.E + c;
 #pragma unroll
@@ -65,6 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const Class
   const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
   const StepConstT<float> sc = make_step_const(cc, a.dt);
+  const HalfInvT<float> A = half_step_inverse(P, sc.h2);
   const int K = a.ckpt_every, S = a.substeps;
   const int nseg = (a.T + K - 1) / K;
   float lam[D];
@@ -101,7 +103,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const Class
             fs[i] = fma_t(sc.rho, fs[i] - fcmd[i], fcmd[i]);
           }
         }
-        rk4_substep<N, LAG>(x, P, gcmd, dg, sc);
+        rk4_substep<N, LAG>(x, P, A, gcmd, dg, sc);
       }
     }
     // reverse sweep over the segment

@@ -55,6 +55,7 @@ __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickItem* __re
 #pragma unroll
     for (int i = 0; i < D; ++i) x[i] = it.block[i * kPageEnvs + lane];
     const EnvConst P = load_env_const(it.block + Dmax * kPageEnvs, kPageEnvs, lane);
+    const HalfInvT<float> A = half_step_inverse(P, sc.h2);
     const float* af = it.actions + (tick - it.t0) * n_max * it.ld + col;
     float act[N], fcmd[N], gcmd[6];
 #pragma unroll
@@ -63,7 +64,7 @@ __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickItem* __re
     command_wrench<N>(cc, fcmd, gcmd);
     // substeps is the server's S (cc.rho_s = rho^S) or, for the FIFO plain
     // baseline, 1 (rho)
-    control_step<N, LAG>(x, P, cc, fcmd, gcmd, sc, substeps, substeps == 1 ? cc.rho : cc.rho_s);
+    control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, substeps, substeps == 1 ? cc.rho : cc.rho_s);
 #pragma unroll
     for (int i = 0; i < D; ++i) it.block[i * kPageEnvs + lane] = x[i];
   }

@@ -70,6 +70,7 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
     P = load_env_const(a.derived, a.Ep, j);
   }
   const StepConstT<float> sc = make_step_const(cc, a.dt);
+  const HalfInvT<float> A = half_step_inverse(P, sc.h2);
   for (int t = 0; t < n_ctrl; ++t) {
     double s_dist = 0.0, m_dist = 0.0, s_ke = 0.0, n_bad = 0.0;
     if (active) {
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
       for (int i = 0; i < N; ++i) act[i] = af[i * a.E];
       thrust_command<N>(cc, act, fcmd);
       command_wrench<N>(cc, fcmd, gcmd);
-      control_step<N, LAG>(x, P, cc, fcmd, gcmd, sc, substeps, PLAIN ? cc.rho : cc.rho_s);
+      control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, substeps, PLAIN ? cc.rho : cc.rho_s);
       if (a.traj) {
         float* tf = a.traj + (int64_t)t * a.D * a.E + c;
 #pragma unroll

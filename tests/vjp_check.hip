@@ -85,7 +85,8 @@ double control_step_dot(const ClassConst& cc, const EnvConstT<double>& P, const 
   for (int i = 0; i < D; ++i) x[i] = x0[i];
   thrust_command<N>(cc, a, fcmd);
   command_wrench<N>(cc, fcmd, gcmd);
-  control_step<N, LAG>(x, P, cc, fcmd, gcmd, make_step_const_host(cc, dt), S, (double)cc.rho_s);
+  const StepConstT<double> sc = make_step_const_host(cc, dt);
+  control_step<N, LAG>(x, P, half_step_inverse(P, sc.h2), cc, fcmd, gcmd, sc, S, (double)cc.rho_s);
   double d = 0;
   for (int i = 0; i < D; ++i) d += lam[i] * x[i];
   return d;
@@ -132,7 +133,7 @@ void check_case(unsigned seed, int map, int S, double dt) {
       xs[s][i] = fs[i - 13];
       fs[i - 13] = sc.rho * (fs[i - 13] - fcmd[i - 13]) + fcmd[i - 13];
     }
-    rk4_substep<N, LAG>(x, P, gcmd, dg, sc);
+    rk4_substep<N, LAG>(x, P, half_step_inverse(P, sc.h2), gcmd, dg, sc);
   }
   double lam[D], fcb[N] = {0}, gcb[6] = {0}, ab[N];
   for (int i = 0; i < D; ++i) lam[i] = lam_out[i];

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define MG_ABI_VERSION 1u
+#define MG_ABI_VERSION 2u
 #define MG_MAX_THRUSTERS 8
 #define MG_MAX_CLASSES 16
 #define MG_NUM_PARAMS 23  /* m, Ixx, Iyy, Izz, M_A(6), D_L(6), D_Q(6), B */
@@ -224,6 +224,12 @@ mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, 
  *   fifo_plain     1: baseline mode -- one request at a time, plain kernel
  *                  (one launch per sub-step); same results
  *   max_queue      bound of the admission queue (0 -> 65536)
+ *   reserve_bytes  page memory (>= 0) to create at start (at most the cap),
+ *                  with pinned staging for up to 4096 pages joining or
+ *                  leaving per tick, so that serving within it allocates
+ *                  nothing; 0: pages are created on demand in slabs of 1024
+ *                  and staging grows as needed.  Creation fails with
+ *                  MG_ERR_OOM if the reservation cannot be had.
  * mg_request (everything the client passes stays owned by the client and
  * must stay valid until the request completes)
  *   n_envs, n_steps  env count (>= 1) and control steps (>= 1; 1 = a step request)
@@ -249,6 +255,7 @@ typedef struct {
   double mem_fraction;
   int32_t fifo_plain;
   int32_t max_queue;
+  int64_t reserve_bytes;
 } mg_server_config;
 
 typedef struct {
@@ -267,11 +274,14 @@ typedef struct {
 /* Server counters: requests completed / rejected, ticks issued, env control
  * steps done, envs active now and at most, requests queued now, the page cap
  * and pages created; host time spent issuing ticks and blocked waiting for the
- * GPU (ns, summed); mean and max time from arrival to admission (ns). */
+ * GPU (ns, summed); mean and max time from arrival to admission (ns); the
+ * longest host time spent issuing one tick (ns); how many times a staging
+ * buffer had to grow (each growth allocates). */
 typedef struct {
   int64_t completed, rejected, ticks, env_steps, active_envs, max_active_envs, queued;
   int64_t cap_pages, created_pages;
   int64_t issue_ns, wait_ns, mean_queue_ns, max_queue_ns;
+  int64_t max_issue_ns, grow_events;
 } mg_server_stats;
 
 uint64_t mg_clock_ns(void);

@@ -46,14 +46,8 @@ class PagePool {
   // or the slab allocator refuses.
   bool allocate(int64_t n, std::vector<int64_t>& out) {
     if (n < 0 || !fits(n)) return false;
-    while ((int64_t)free_.size() < n) {
-      const int64_t room = cap_ - created_;
-      if (room <= 0) return false;
-      const int64_t add = room < slab_ ? room : slab_;
-      if (!alloc_(created_, add)) return false;
-      for (int64_t p = created_ + add - 1; p >= created_; --p) free_.push_back(p);
-      created_ += add;
-    }
+    while ((int64_t)free_.size() < n)
+      if (!add_slab()) return false;
     for (int64_t i = 0; i < n; ++i) {
       out.push_back(free_.back());
       free_.pop_back();
@@ -67,7 +61,27 @@ class PagePool {
     used_ -= (int64_t)pages.size();
   }
 
+  // Creates slabs up front until at least min(n_pages, cap) pages exist, so
+  // that later allocations need no allocator call; false if the allocator
+  // refuses (the slabs created so far stay).
+  bool reserve(int64_t n_pages) {
+    const int64_t want = n_pages < cap_ ? n_pages : cap_;
+    while (created_ < want)
+      if (!add_slab()) return false;
+    return true;
+  }
+
  private:
+  bool add_slab() {
+    const int64_t room = cap_ - created_;
+    if (room <= 0) return false;
+    const int64_t add = room < slab_ ? room : slab_;
+    if (!alloc_(created_, add)) return false;
+    for (int64_t p = created_ + add - 1; p >= created_; --p) free_.push_back(p);
+    created_ += add;
+    return true;
+  }
+
   int64_t cap_, slab_;
   SlabAlloc alloc_;
   int64_t used_ = 0, created_ = 0;

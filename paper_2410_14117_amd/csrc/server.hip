@@ -26,6 +26,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 using namespace mg;
@@ -65,27 +66,39 @@ struct Record {
   bool finished = false;
 };
 
+// Pinned host buffer + device buffer of the same capacity.  Growth keeps the
+// outgrown pair until release(): freeing device memory waits for the whole
+// device, which would stall the tick pipeline, so the scheduler never frees;
+// capacities double, so the retired pairs add up to less than the live one.
 template <class T>
-struct Mirror {   // pinned host buffer + device buffer of the same capacity
+struct Mirror {
   T* h = nullptr;
   T* d = nullptr;
   size_t cap = 0;
+  std::vector<std::pair<T*, T*>> outgrown;
   bool grow(size_t need) {
     if (need <= cap) return true;
     size_t c = std::max<size_t>(need, cap * 2 + 64);
-    release();
-    if (hipHostMalloc((void**)&h, c * sizeof(T), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&d, c * sizeof(T)) != hipSuccess) {
+    T *nh = nullptr, *nd = nullptr;
+    if (hipHostMalloc((void**)&nh, c * sizeof(T), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&nd, c * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
-      release();
+      if (nh) (void)hipHostFree(nh);
       return false;
     }
+    if (h || d) outgrown.emplace_back(h, d);
+    h = nh;
+    d = nd;
     cap = c;
     return true;
   }
   void release() {
-    if (h) (void)hipHostFree(h);
-    if (d) (void)hipFree(d);
+    outgrown.emplace_back(h, d);
+    for (auto& hd : outgrown) {
+      if (hd.first) (void)hipHostFree(hd.first);
+      if (hd.second) (void)hipFree(hd.second);
+    }
+    outgrown.clear();
     h = nullptr;
     d = nullptr;
     cap = 0;
@@ -173,6 +186,7 @@ struct mg_server {
   std::atomic<int64_t> completed{0}, rejected{0}, ticks{0}, env_steps{0}, active_envs{0},
       max_active_envs{0}, queued{0};
   std::atomic<int64_t> issue_ns{0}, wait_ns{0}, queue_ns{0}, max_queue_ns{0}, admitted_n{0};
+  std::atomic<int64_t> max_issue_ns{0}, grow_events{0};
 };
 
 namespace {
@@ -280,6 +294,16 @@ Mirror<float>* take_out_buffer(mg_server* S) {
   return S->out_all.back();
 }
 
+// Mirror::grow, counting the growths that allocate (they cost host time in the
+// scheduler; the counter shows whether a run was served from warm buffers).
+template <class T>
+bool grow_counted(mg_server* S, Mirror<T>& m, size_t need) {
+  const size_t before = m.cap;
+  const bool ok = m.grow(need);
+  if (m.cap != before) S->grow_events.fetch_add(1);
+  return ok;
+}
+
 // Grows the device tick list to hold `need` entries per class: waits for the
 // stream, copies the host mirror and re-captures every slot's graph.
 bool grow_list(mg_server* S, size_t need, std::vector<ServeTickItem>& host) {
@@ -330,7 +354,8 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
     size_t need = 0;
     for (int c = 0; c < S->n_classes; ++c) need = std::max<size_t>(need, S->hw[c]);
     if (need > S->list_cap && !grow_list(S, need, list_h)) return false;
-    if (!sl.init.grow(n_init) || !sl.cols_stage.grow(n_init * kPageEnvs) || !sl.pre.grow(n_init))
+    if (!grow_counted(S, sl.init, n_init) || !grow_counted(S, sl.cols_stage, n_init * kPageEnvs) ||
+        !grow_counted(S, sl.pre, n_init))
       return fail_server(S, "host/device staging allocation failed");
     size_t k = 0;
     for (Request* r : admitted) {
@@ -398,7 +423,8 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
   }
   if (!sl.retiring.empty()) {
     sl.out = take_out_buffer(S);
-    if (!sl.gather.grow(n_gat) || !sl.out->grow(n_out) || !sl.post.grow(n_gat))
+    if (!grow_counted(S, sl.gather, n_gat) || !grow_counted(S, *sl.out, n_out) ||
+        !grow_counted(S, sl.post, n_gat))
       return fail_server(S, "gather staging allocation failed");
     size_t k = 0, o = 0;
     for (Request* r : sl.retiring) {
@@ -540,7 +566,9 @@ void scheduler(mg_server* S) {
     S->next_slot = (S->next_slot + 1) % mg_server::kSlots;
     const uint64_t t_issue = clock_ns();
     if (!launch_tick(S, S->slots[k], admitted, list_h)) break;
-    S->issue_ns.fetch_add((int64_t)(clock_ns() - t_issue));
+    const int64_t dt_issue = (int64_t)(clock_ns() - t_issue);
+    S->issue_ns.fetch_add(dt_issue);
+    if (dt_issue > S->max_issue_ns.load()) S->max_issue_ns.store(dt_issue);
     S->inflight.push_back(k);
   }
   // drain: anything left fails (device error or shutdown)
@@ -593,6 +621,7 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   if (cfg->n_classes < 1 || cfg->n_classes > MG_MAX_CLASSES || !cfg->classes)
     return bad(MG_ERR_INVALID, "n_classes outside 1..16 or classes NULL");
   if (!(cfg->dt_sub > 0.0) || cfg->substeps < 1) return bad(MG_ERR_INVALID, "dt_sub / substeps");
+  if (cfg->reserve_bytes < 0) return bad(MG_ERR_INVALID, "reserve_bytes < 0");
   for (int k = 0; k < cfg->n_classes; ++k) {
     const mg_vehicle& v = cfg->classes[k];
     if (v.n_thr < 1 || v.n_thr > MG_MAX_THRUSTERS || (v.thr_map != 0 && v.thr_map != 1) ||
@@ -660,7 +689,7 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   }
   S->free_entries.resize(S->n_classes);
   S->hw.assign(S->n_classes, 0);
-  S->list_cap = 1024;
+  S->list_cap = 8192;   // entries per class (64 envs each); grows by doubling
   {
     std::vector<ServeTickItem> z(S->list_cap * S->n_classes);
     std::memset(z.data(), 0, z.size() * sizeof(ServeTickItem));
@@ -678,6 +707,25 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
       (void)hipGetLastError();
       mg_server_destroy(S.release());
       return bad(MG_ERR_DEVICE, "tick slot initialisation failed");
+    }
+  }
+  if (cfg->reserve_bytes > 0) {
+    // pages up front, and staging for up to 4096 pages joining or leaving per
+    // tick, so that serving within the reservation allocates nothing
+    bool ok = S->pool->reserve(cfg->reserve_bytes / page_bytes);
+    const size_t items = (size_t)std::min<int64_t>(4096, S->pool->created_pages());
+    for (auto& sl : S->slots)
+      ok = ok && sl.init.grow(items) && sl.cols_stage.grow(items * kPageEnvs) &&
+           sl.pre.grow(items) && sl.post.grow(items) && sl.gather.grow(items);
+    const size_t out_floats = std::min<size_t>(items * kPageEnvs * (size_t)S->D, (size_t)1 << 22);
+    for (int i = 0; ok && i < mg_server::kSlots + 2; ++i) {
+      S->out_all.push_back(new Mirror<float>());
+      S->out_pool.push_back(S->out_all.back());
+      ok = S->out_all.back()->grow(out_floats);
+    }
+    if (!ok) {
+      mg_server_destroy(S.release());
+      return bad(MG_ERR_OOM, "could not reserve the requested page memory and staging");
     }
   }
   S->deliver_thr = std::thread(deliverer, S.get());
@@ -787,6 +835,8 @@ mg_status mg_server_get_stats(const mg_server* S, mg_server_stats* out) {
   const int64_t na = S->admitted_n.load();
   out->mean_queue_ns = na ? S->queue_ns.load() / na : 0;
   out->max_queue_ns = S->max_queue_ns.load();
+  out->max_issue_ns = S->max_issue_ns.load();
+  out->grow_events = S->grow_events.load();
   return S->broken ? MG_ERR_DEVICE : MG_OK;
 }
 

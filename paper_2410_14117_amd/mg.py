@@ -12,7 +12,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MG_LIBRARY") or os.path.join(HERE, "libmg.so")
 
-MG_ABI_VERSION = 1
+MG_ABI_VERSION = 2
 MAX_THR = 8
 NUM_PARAMS = 23
 NUM_THETA = 19
@@ -55,6 +55,7 @@ class MgServerConfig(ctypes.Structure):
         ("substeps", ctypes.c_int32), ("device", ctypes.c_int32),
         ("mem_cap_bytes", ctypes.c_int64), ("mem_fraction", ctypes.c_double),
         ("fifo_plain", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+        ("reserve_bytes", ctypes.c_int64),
     ]
 
 
@@ -71,7 +72,7 @@ class MgServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("completed", "rejected", "ticks", "env_steps", "active_envs", "max_active_envs",
                  "queued", "cap_pages", "created_pages", "issue_ns", "wait_ns", "mean_queue_ns",
-                 "max_queue_ns")]
+                 "max_queue_ns", "max_issue_ns", "grow_events")]
 
 
 _vp = ctypes.c_void_p
@@ -351,7 +352,7 @@ class Server:
     """Continuous-batching serving loop on one GPU (wraps an ``mg_server``)."""
 
     def __init__(self, classes, dt_sub, substeps, device=0, mem_cap_bytes=0, mem_fraction=0.0,
-                 fifo_plain=False, max_queue=0):
+                 fifo_plain=False, max_queue=0, reserve_bytes=0):
         import threading
         L = lib()
         if isinstance(classes, dict):
@@ -368,6 +369,7 @@ class Server:
         cfg.mem_fraction = float(mem_fraction)
         cfg.fifo_plain = 1 if fifo_plain else 0
         cfg.max_queue = int(max_queue)
+        cfg.reserve_bytes = int(reserve_bytes)
         h = _vp()
         st = L.mg_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if st != MG_OK:

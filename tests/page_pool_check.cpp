@@ -50,6 +50,19 @@ int main() {
   PagePool p2(8, 8, [&](int64_t, int64_t) { return false; });
   std::vector<int64_t> e;
   CHECK(!p2.allocate(1, e) && e.empty() && p2.used_pages() == 0 && p2.created_pages() == 0);
+  // reserve creates slabs up front (at most up to the cap); allocations then reuse them
+  std::vector<std::pair<long, long>> s3;
+  PagePool p3(10, 4, [&](int64_t first, int64_t n) {
+    s3.push_back({first, n});
+    return true;
+  });
+  CHECK(p3.reserve(5) && p3.created_pages() == 8 && s3.size() == 2 && p3.used_pages() == 0);
+  std::vector<int64_t> f;
+  CHECK(p3.allocate(8, f) && s3.size() == 2);                         // no new slab
+  CHECK(p3.reserve(100) && p3.created_pages() == 10 && s3.size() == 3);  // capped
+  CHECK(p3.reserve(3) && s3.size() == 3);                              // nothing to add
+  PagePool p4(8, 4, [&](int64_t, int64_t) { return false; });
+  CHECK(!p4.reserve(4) && p4.created_pages() == 0);
   std::printf("page pool check: %d failures\n", failures);
   return failures ? 1 : 0;
 }

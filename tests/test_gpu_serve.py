@@ -138,6 +138,31 @@ def test_memory_cap_admission(mgmod, pools):
         np.testing.assert_array_equal(u, v)
 
 
+def test_reserved_pages_are_created_up_front(mgmod, pools):
+    """reserve_bytes creates page memory at start (capped at the cap); admissions within it
+    create no pages; results equal those of an on-demand server bitwise."""
+    say("serve reserve")
+    pb = mgmod.page_bytes(D)
+    srv = mgmod.Server(CLASSES, DT, S, mem_cap_bytes=3000 * pb, reserve_bytes=2100 * pb)
+    s0 = srv.stats()
+    assert s0["created_pages"] >= 2100 and s0["created_pages"] <= 3000
+    reqs = [(k * 4000, 3000, 5) for k in range(6)]          # ~50 pages each
+    outs, _ = _serve(srv, pools, reqs)
+    s1 = srv.stats()
+    assert s1["created_pages"] == s0["created_pages"] and s1["completed"] == 6
+    srv.close()
+    capped = mgmod.Server(CLASSES, DT, S, mem_cap_bytes=40 * pb, reserve_bytes=10 ** 9)
+    assert capped.stats()["created_pages"] == 40
+    capped.close()
+    with pytest.raises(mgmod.MgError):
+        mgmod.Server(CLASSES, DT, S, reserve_bytes=-1)
+    ref = mgmod.Server(CLASSES, DT, S)
+    outs_ref, _ = _serve(ref, pools, reqs)
+    ref.close()
+    for u, v in zip(outs, outs_ref):
+        np.testing.assert_array_equal(u, v)
+
+
 def test_request_joins_mid_flight(mgmod, pools):
     """A short request submitted while a long one runs finishes first (continuous batching)."""
     say("serve join")

@@ -34,16 +34,17 @@ PEAK_HBM = 8.0e12
 
 def substep_flops(n_thr, lag, substeps):
     """Flops of one env-substep as the kernel formulates it (FMA = 2, one per add/mul):
-    four right-hand sides up to the residual tau - C nu - D nu - g (144 each), the RK4
-    stages and combination of the kinematic rows (73) and of the velocity rows through
-    the pre-scaled inverse (h/2) M^-1 (122), the quaternion renormalisation (12) and,
-    with a thruster lag, the closed-form lag stage wrenches and the carried lag wrench
-    (48); plus, per control step, the throttle map, the command wrench, the lag wrench
-    and the end-of-control-step lag states (29 N - 12; 14 N - 6 without lag) spread over
-    the sub-steps."""
-    core = 4 * 144 + 73 + 122 + 12
+    four right-hand sides up to the residual tau - C nu - D nu - g given the momentum
+    M nu (130 each), the RK4 stages and combination of the kinematic rows (73), of the
+    velocity rows through the pre-scaled inverse (h/2) M^-1 (122) and of the carried
+    momentum (48), the quaternion renormalisation (12) and, with a thruster lag, the
+    closed-form lag stage wrenches and the carried lag wrench (48); plus, per control
+    step, the throttle map, the command wrench, the lag wrench, the end-of-control-step
+    lag states and the momentum (29 N + 2; 14 N + 8 without lag) spread over the
+    sub-steps."""
+    core = 4 * 130 + 73 + 122 + 48 + 12
     lag_part = 48 if lag else 0
-    per_ctrl = (29 * n_thr - 12) if lag else (14 * n_thr - 6)
+    per_ctrl = (29 * n_thr + 2) if lag else (14 * n_thr + 8)
     return core + lag_part + per_ctrl / substeps
 
 

@@ -175,11 +175,27 @@ __host__ __device__ __forceinline__ void command_wrench(const ClassConst& cc, co
 //         C(nu) nu = [w x a ; v x a + w x b], [a; b] = M nu (Kirchhoff form of
 //         the skew-symmetric C_RB + C_A), D diagonal linear + quadratic,
 //         g = -[(W-B) k ; h x k], k = R(q)^T e3, h = (0, 0, W z_g - B z_b).
-// rhs_residual writes the kinematic rows xd[0..6] and the residual
-// r = tau - C nu - D nu - g; rhs_core applies M^-1 to it.  xd may not alias x.
+// The momentum [a; b] = M nu of the structured M, ordered (u, v, w, p, q, r).
 template <class T>
-__host__ __device__ __forceinline__ void rhs_residual(const T* x, T* xd, T (&res)[6],
-                                                      const EnvConstT<T>& P, const T (&tau)[6]) {
+__host__ __device__ __forceinline__ void momentum(const EnvConstT<T>& P, const T* nu,
+                                                  T (&mom)[6]) {
+  const T u = nu[0], v = nu[1], w = nu[2], p = nu[3], q = nu[4], r = nu[5];
+  mom[0] = fma_t(P.Muq, q, P.Muu * u);
+  mom[1] = fma_t(P.Mvp, p, P.Mvv * v);
+  mom[2] = P.Mww * w;
+  mom[3] = fma_t(P.Mpp, p, P.Mvp * v);
+  mom[4] = fma_t(P.Mqq, q, P.Muq * u);
+  mom[5] = P.Mrr * r;
+}
+
+// rhs_residual_m writes the kinematic rows xd[0..6] and the residual
+// r = tau - C nu - D nu - g given the momentum mom = M nu of the state x;
+// rhs_residual forms mom itself; rhs_core applies M^-1 to the residual.  xd
+// may not alias x.
+template <class T>
+__host__ __device__ __forceinline__ void rhs_residual_m(const T* x, const T (&mom)[6], T* xd,
+                                                        T (&res)[6], const EnvConstT<T>& P,
+                                                        const T (&tau)[6]) {
   const T qw = x[3], qx = x[4], qy = x[5], qz = x[6];
   const T u = x[7], v = x[8], w = x[9], p = x[10], q = x[11], r = x[12];
 
@@ -200,9 +216,7 @@ __host__ __device__ __forceinline__ void rhs_residual(const T* x, T* xd, T (&res
   const T k1 = fma_t(y2, qz, x2 * qw);
   const T k2 = fma_t(-y2, qy, fma_t(-x2, qx, T(1)));
 
-  // [a; b] = M nu
-  const T au = fma_t(P.Muq, q, P.Muu * u), av = fma_t(P.Mvp, p, P.Mvv * v), aw = P.Mww * w;
-  const T bp = fma_t(P.Mpp, p, P.Mvp * v), bq = fma_t(P.Mqq, q, P.Muq * u), br = P.Mrr * r;
+  const T au = mom[0], av = mom[1], aw = mom[2], bp = mom[3], bq = mom[4], br = mom[5];
   // damping coefficients d_L + d_Q |nu|
   const T e0 = fma_t(P.dq[0], abs_t(u), P.dl[0]);
   const T e1 = fma_t(P.dq[1], abs_t(v), P.dl[1]);
@@ -223,6 +237,14 @@ __host__ __device__ __forceinline__ void rhs_residual(const T* x, T* xd, T (&res
 }
 
 template <class T>
+__host__ __device__ __forceinline__ void rhs_residual(const T* x, T* xd, T (&res)[6],
+                                                      const EnvConstT<T>& P, const T (&tau)[6]) {
+  T mom[6];
+  momentum(P, x + 7, mom);
+  rhs_residual_m(x, mom, xd, res, P, tau);
+}
+
+template <class T>
 __host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvConstT<T>& P,
                                                   const T (&tau)[6]) {
   T r[6];
@@ -240,7 +262,8 @@ __host__ __device__ __forceinline__ void rhs_core(const T* x, T* xd, const EnvCo
 // launch, so the RK4 stage velocities come from the residuals in FMAs alone
 // (nu + (h/2) M^-1 r = nu + A r, nu + h M^-1 r = nu + 2 A r, and the
 // combination (h/6) M^-1 (r1 + 2 r2 + 2 r3 + r4) = (1/3) A (...), M^-1 being
-// constant over the sub-step).
+// constant over the sub-step).  The momenta follow without M: M (nu + c M^-1 r)
+// = M nu + c r.
 template <class T>
 struct HalfInvT {
   T uu, vv, ww, pp, qq, rr, uq, vp;
@@ -322,8 +345,12 @@ __host__ __device__ __forceinline__ void begin_control_step(const ClassConst& cc
   }
 }
 
+// m is the momentum M nu of the state, carried from sub-step to sub-step of a
+// control step (formed by control_step): the stage momenta are m + c r and
+// the sub-step ends with m <- m + (h/6)(r1 + 2 r2 + 2 r3 + r4), equal to
+// M nu of the new state in exact arithmetic.
 template <int N, bool LAG, class T>
-__host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P,
+__host__ __device__ __forceinline__ void rk4_substep(T* x, T (&m)[6], const EnvConstT<T>& P,
                                                      const HalfInvT<T>& A, const T (&gcmd)[6],
                                                      T (&dg)[6], const StepConstT<T>& sc) {
   T tau[6];
@@ -340,42 +367,51 @@ __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P
   auto f1 = [&](int i) { return (i >= 3) ? sc.dtq : sc.dt; };
   auto f6 = [&](int i) { return (i >= 3) ? sc.h6q : sc.h6; };
   // acc: kinematic rates (rows 0..6) and residuals (rows 7..12) summed with
-  // the RK4 weights 1, 2, 2, 1
-  T k[7], r[6], X[13], acc[13], t[6];
-  rhs_residual(x, k, r, P, tau);
+  // the RK4 weights 1, 2, 2, 1; ms: the stage momentum
+  T k[7], r[6], X[13], acc[13], t[6], ms[6];
+  rhs_residual_m(x, m, k, r, P, tau);
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
     acc[i] = k[i];
     X[i] = fma_t(f2(i), k[i], x[i]);
   }
 #pragma unroll
-  for (int i = 0; i < 6; ++i) acc[7 + i] = r[i];
+  for (int i = 0; i < 6; ++i) {
+    acc[7 + i] = r[i];
+    ms[i] = fma_t(sc.h2, r[i], m[i]);
+  }
   add_inv(A, r, x + 7, X + 7);
   if constexpr (LAG) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s2, dg[j], gcmd[j]);
   }
-  rhs_residual(X, k, r, P, tau);
+  rhs_residual_m(X, ms, k, r, P, tau);
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
     acc[i] = fma_t(sc.two, k[i], acc[i]);
     X[i] = fma_t(f2(i), k[i], x[i]);
   }
 #pragma unroll
-  for (int i = 0; i < 6; ++i) acc[7 + i] = fma_t(sc.two, r[i], acc[7 + i]);
+  for (int i = 0; i < 6; ++i) {
+    acc[7 + i] = fma_t(sc.two, r[i], acc[7 + i]);
+    ms[i] = fma_t(sc.h2, r[i], m[i]);
+  }
   add_inv(A, r, x + 7, X + 7);
   if constexpr (LAG) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s3, dg[j], gcmd[j]);
   }
-  rhs_residual(X, k, r, P, tau);
+  rhs_residual_m(X, ms, k, r, P, tau);
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
     acc[i] = fma_t(sc.two, k[i], acc[i]);
     X[i] = fma_t(f1(i), k[i], x[i]);
   }
 #pragma unroll
-  for (int i = 0; i < 6; ++i) acc[7 + i] = fma_t(sc.two, r[i], acc[7 + i]);
+  for (int i = 0; i < 6; ++i) {
+    acc[7 + i] = fma_t(sc.two, r[i], acc[7 + i]);
+    ms[i] = fma_t(sc.dt, r[i], m[i]);
+  }
   mul_inv(A, r, t);
 #pragma unroll
   for (int i = 0; i < 6; ++i) X[7 + i] = fma_t(sc.two, t[i], x[7 + i]);
@@ -383,11 +419,14 @@ __host__ __device__ __forceinline__ void rk4_substep(T* x, const EnvConstT<T>& P
 #pragma unroll
     for (int j = 0; j < 6; ++j) tau[j] = fma_t(sc.s4, dg[j], gcmd[j]);
   }
-  rhs_residual(X, k, r, P, tau);
+  rhs_residual_m(X, ms, k, r, P, tau);
 #pragma unroll
   for (int i = 0; i < 7; ++i) x[i] = fma_t(f6(i), acc[i] + k[i], x[i]);
 #pragma unroll
-  for (int i = 0; i < 6; ++i) r[i] += acc[7 + i];
+  for (int i = 0; i < 6; ++i) {
+    r[i] += acc[7 + i];
+    m[i] = fma_t(sc.h6, r[i], m[i]);
+  }
   mul_inv(A, r, t);
 #pragma unroll
   for (int i = 0; i < 6; ++i) x[7 + i] = fma_t(sc.third, t[i], x[7 + i]);
@@ -415,10 +454,11 @@ __host__ __device__ __forceinline__ void control_step(T* x, const EnvConstT<T>& 
                                                       const HalfInvT<T>& A, const ClassConst& cc,
                                                       const T (&fcmd)[N], const T (&gcmd)[6],
                                                       const StepConstT<T>& sc, int S, T rho_s) {
-  T dg[6];
+  T dg[6], m[6];
   begin_control_step<N, LAG>(cc, x, fcmd, dg, rho_s);
+  momentum(P, x + 7, m);
   MG_UNROLL_(MG_SUBSTEP_UNROLL)
-  for (int s = 0; s < S; ++s) rk4_substep<N, LAG>(x, P, A, gcmd, dg, sc);
+  for (int s = 0; s < S; ++s) rk4_substep<N, LAG>(x, m, P, A, gcmd, dg, sc);
 }
 
 }  // namespace mg

@@ -92,6 +92,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const Class
         for (int i = 0; i < N; ++i) fs[i] = x[13 + i];
       }
       begin_control_step<N, LAG>(cc, x, fcmd, dg, cc.rho_s);
+      float m[6];
+      momentum(P, x + 7, m);
       for (int s = 0; s < S; ++s) {
         float* sb = a.segbuf + (int64_t)((t - t0) * S + s) * D * a.Ep + j;
 #pragma unroll
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const Class
             fs[i] = fma_t(sc.rho, fs[i] - fcmd[i], fcmd[i]);
           }
         }
-        rk4_substep<N, LAG>(x, P, A, gcmd, dg, sc);
+        rk4_substep<N, LAG>(x, m, P, A, gcmd, dg, sc);
       }
     }
     // reverse sweep over the segment

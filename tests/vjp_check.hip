@@ -127,13 +127,15 @@ void check_case(unsigned seed, int map, int S, double dt) {
   double dg[6];
   begin_control_step<N, LAG>(cc, x, fcmd, dg, (double)cc.rho_s);
   const StepConstT<double> sc = make_step_const_host(cc, dt);
+  double m[6];
+  momentum(P, x + 7, m);
   for (int s = 0; s < S; ++s) {
     for (int i = 0; i < 13; ++i) xs[s][i] = x[i];
     for (int i = 13; i < D; ++i) {
       xs[s][i] = fs[i - 13];
       fs[i - 13] = sc.rho * (fs[i - 13] - fcmd[i - 13]) + fcmd[i - 13];
     }
-    rk4_substep<N, LAG>(x, P, half_step_inverse(P, sc.h2), gcmd, dg, sc);
+    rk4_substep<N, LAG>(x, m, P, half_step_inverse(P, sc.h2), gcmd, dg, sc);
   }
   double lam[D], fcb[N] = {0}, gcb[6] = {0}, ab[N];
   for (int i = 0; i < D; ++i) lam[i] = lam_out[i];

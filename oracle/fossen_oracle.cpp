@@ -37,7 +37,15 @@
  *
  * Episode statistics per control step (the Task-1 error of Eq. (4), kinetic
  * energy, non-finite count) and the circle-tracking loss are computed in FP64.
+ *
+ * The Gym-style tasks of Sec. III (station keeping, circle, helix and
+ * lemniscate tracking): the reference trajectories, the observation of
+ * Eq. (2) (pose errors against the next m reference points, then nu), the
+ * position error of Eq. (4) and the episode bookkeeping (counter, termination,
+ * truncation, automatic reset) are written out step by step in FP64; their
+ * readings are listed with the design notes.
  */
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -89,6 +97,20 @@ struct OrVehicle {
   double mass, inertia[3], r_g[3], r_b[3], added_mass[6], d_lin[6], d_quad[6], buoyancy;
   double thr_pos[kMaxThr][3], thr_dir[kMaxThr][3], f_max, thr_tau;
   int32_t n_thr, thr_map;
+};
+/* Task description (Sec. III).  Mirrored field-for-field by the ctypes shim.
+ *   task           0 station keeping, 1 circle, 2 helix, 3 lemniscate
+ *   lookahead      m reference points in the observation (tracking tasks)
+ *   radius, omega  curve size (m) and rate of its parameter (rad/s)
+ *   climb_rate     helix vertical rate (m/s along NED z)
+ *   lookahead_dt   time between the look-ahead points (s)
+ *   episode_steps  control steps per episode (truncation)
+ *   max_error      position error (m) above which an episode terminates; 0: never */
+struct OrTask {
+  int32_t task, lookahead;
+  double radius, omega, climb_rate, lookahead_dt;
+  int32_t episode_steps, pad;
+  double max_error;
 };
 }
 
@@ -406,7 +428,104 @@ T tracking_loss(const T* x, const double* pr, const double* qr, double lam) {
 
 int resolve_threads(int nthreads) { return nthreads > 0 ? nthreads : omp_get_max_threads(); }
 
+/* ---- tasks of Sec. III ------------------------------------------------------- */
+
+constexpr double kPi = 3.14159265358979323846;
+
+/* Reference point p_r and reference heading psi_r at time t (s since the
+ * episode began) of one env: centre c, curve phase ph, station-keeping yaw.
+ * The curve parameter is s = omega t + ph; the reference heading of a
+ * tracking task is the direction of the reference velocity dp_r/dt in the
+ * horizontal plane, written out by the chain rule. */
+void task_reference(const OrTask& tk, const double* c, double ph, double yaw, double t,
+                    double* pr, double* psi) {
+  const double R = tk.radius, w = tk.omega, s = w * t + ph;
+  double off[3] = {0.0, 0.0, 0.0}, vel[3] = {0.0, 0.0, 0.0};
+  switch (tk.task) {
+    case 0:  // station keeping: a fixed point and heading
+      for (int i = 0; i < 3; ++i) pr[i] = c[i];
+      *psi = yaw;
+      return;
+    case 1:  // circle in the horizontal plane
+    case 2:  // helix: the circle plus a constant vertical rate
+      off[0] = R * std::cos(s);
+      off[1] = R * std::sin(s);
+      vel[0] = -R * w * std::sin(s);
+      vel[1] = R * w * std::cos(s);
+      if (tk.task == 2) {
+        off[2] = tk.climb_rate * t;
+        vel[2] = tk.climb_rate;
+      }
+      break;
+    default: {  // lemniscate of Bernoulli, (x^2 + y^2)^2 = R^2 (x^2 - y^2)
+      const double sn = std::sin(s), cs = std::cos(s), den = 1.0 + sn * sn;
+      off[0] = R * cs / den;
+      off[1] = R * sn * cs / den;
+      // quotient rule on cos s / (1 + sin^2 s) and sin s cos s / (1 + sin^2 s)
+      const double dxds = R * (-sn * den - cs * 2.0 * sn * cs) / (den * den);
+      const double dyds = R * ((cs * cs - sn * sn) * den - sn * cs * 2.0 * sn * cs) / (den * den);
+      vel[0] = w * dxds;
+      vel[1] = w * dyds;
+      break;
+    }
+  }
+  for (int i = 0; i < 3; ++i) pr[i] = c[i] + off[i];
+  *psi = std::atan2(vel[1], vel[0]);
+}
+
+/* Roll, pitch, yaw of the ZYX convention, R(q) = Rz(psi) Ry(theta) Rx(phi),
+ * read off the rotation matrix. */
+void euler_zyx(const double* q, double* rpy) {
+  double R[3][3];
+  rotation(q, R);
+  const double s = std::max(-1.0, std::min(1.0, -R[2][0]));
+  rpy[0] = std::atan2(R[2][1], R[2][2]);
+  rpy[1] = std::asin(s);
+  rpy[2] = std::atan2(R[1][0], R[0][0]);
+}
+
+/* Angle wrapped into (-pi, pi]. */
+double wrap_angle(double a) {
+  double r = std::remainder(a, 2.0 * kPi);
+  if (r <= -kPi) r += 2.0 * kPi;
+  return r;
+}
+
+int task_obs_dim(const OrTask& tk) { return tk.task == 0 ? 12 : 6 * tk.lookahead + 6; }
+
+/* Observation of Eq. (2) at episode time t: the pose error against the
+ * target (station keeping) or against each of the next m reference points at
+ * t + i dl, i = 1..m (tracking), the reference attitude being level and
+ * headed along the reference heading; then nu. */
+void task_observe(const OrTask& tk, const double* x, const double* c, double ph, double yaw,
+                  double t, double dl, double* obs) {
+  double rpy[3];
+  euler_zyx(x + 3, rpy);
+  const int m = tk.task == 0 ? 1 : tk.lookahead;
+  for (int i = 0; i < m; ++i) {
+    const double ti = tk.task == 0 ? t : t + (i + 1) * dl;
+    double pr[3], psi;
+    task_reference(tk, c, ph, yaw, ti, pr, &psi);
+    for (int k = 0; k < 3; ++k) obs[6 * i + k] = x[k] - pr[k];
+    obs[6 * i + 3] = wrap_angle(rpy[0]);
+    obs[6 * i + 4] = wrap_angle(rpy[1]);
+    obs[6 * i + 5] = wrap_angle(rpy[2] - psi);
+  }
+  for (int k = 0; k < 6; ++k) obs[6 * m + k] = x[7 + k];
+}
+
+/* Position error of Eq. (4) at episode time t: |p - p_r(t)|. */
+double task_error(const OrTask& tk, const double* x, const double* c, double ph, double yaw,
+                  double t) {
+  double pr[3], psi;
+  task_reference(tk, c, ph, yaw, t, pr, &psi);
+  double d2 = 0.0;
+  for (int k = 0; k < 3; ++k) d2 += (x[k] - pr[k]) * (x[k] - pr[k]);
+  return std::sqrt(d2);
+}
+
 }  // namespace
+
 
 /* ======================================================================== */
 /* C entry points (ctypes).  All arrays are FP64, row-major, SoA [comp][env]. */
@@ -670,6 +789,126 @@ int or_jvp(const OrVehicle* v, const double* mult, const double* x0, const doubl
       traj[(size_t)t * Dc + i] = x[i].v;
       dtraj[(size_t)t * Dc + i] = x[i].d;
     }
+  }
+  return 0;
+}
+
+}  // extern "C"
+
+/* ---- tasks of Sec. III (C entry points) ------------------------------------- */
+extern "C" {
+
+/* Reference point pr[3] and heading *psi of one env at episode time t. */
+int or_task_reference(const OrTask* tk, const double* c, double phase, double yaw, double t,
+                      double* pr, double* psi) {
+  if (!tk || tk->task < 0 || tk->task > 3) return -1;
+  task_reference(*tk, c, phase, yaw, t, pr, psi);
+  return 0;
+}
+
+/* ZYX roll, pitch, yaw of the unit quaternion q (scalar first). */
+int or_euler_zyx(const double* q, double* rpy) {
+  euler_zyx(q, rpy);
+  return 0;
+}
+
+/* Observation width of a task: 12 (station keeping) or 6 m + 6 (tracking). */
+int or_task_obs_dim(const OrTask* tk) { return task_obs_dim(*tk); }
+
+/* Observations [obs_dim][E] of the states x [D][E] at episode step k[E]
+ * (time k * dt_ctrl); centre [3][E], phase [E], yaw [E] (or NULL: 0). */
+int or_task_observe(const OrTask* tk, int64_t E, const double* x, int D, const double* center,
+                    const double* phase, const double* yaw, const int32_t* k, double dt_ctrl,
+                    double* obs) {
+  if (!tk || tk->task < 0 || tk->task > 3 || (tk->task != 0 && tk->lookahead < 1)) return -1;
+  if (D < 13 || D > kMaxState) return -1;
+  const int od = task_obs_dim(*tk);
+  const double dl = tk->lookahead_dt > 0.0 ? tk->lookahead_dt : dt_ctrl;
+  for (int64_t e = 0; e < E; ++e) {
+    double xe[kMaxState], c[3], o[6 * 16 + 6];
+    for (int i = 0; i < D; ++i) xe[i] = x[(size_t)i * E + e];
+    for (int i = 0; i < 3; ++i) c[i] = center[(size_t)i * E + e];
+    task_observe(*tk, xe, c, phase[e], yaw ? yaw[e] : 0.0, (k ? k[e] : 0) * dt_ctrl, dl, o);
+    for (int i = 0; i < od; ++i) obs[(size_t)i * E + e] = o[i];
+  }
+  return 0;
+}
+
+/* T Gym-style steps of every env: each step is one control step (S substeps
+ * of dt with the throttle frame held), then the episode counter advances, the
+ * position error of Eq. (4) is taken at the new time, and the episode ends
+ * terminated (done 1: non-finite state, or error above max_error > 0) or
+ * truncated (done 2: episode_steps reached).  An ended episode restarts at
+ * once from the env's column of reset_state [D][E] (NULL: at rest at the
+ * origin, identity attitude, no thrust), with the parameters nominal x
+ * reset_mult [23][E] if given (else unchanged) and the counter at 0; the
+ * observation after the step is that of the new episode.
+ *   x0 [D][E], act [T][nmax][E], mult [23][E] or NULL, k0 [E] or NULL (0)
+ *   obs [(T + 1)][obs_dim][E] (before the first step, then after each),
+ *   err [T][E], done [T][E] (int32), xT [D][E], kT [E] (int32), each or NULL */
+int or_task_rollout(const OrVehicle* classes, int n_classes, const int32_t* env_class, int64_t E,
+                    const double* mult, const double* x0, int D, const double* act, int nmax,
+                    int T, int S, double dt, const OrTask* tk, const double* center,
+                    const double* phase, const double* yaw, const int32_t* k0,
+                    const double* reset_state, const double* reset_mult, double* obs,
+                    double* err, int32_t* done, double* xT, int32_t* kT, int nthreads) {
+  if (E < 0 || T < 0 || S < 1 || n_classes < 1 || D < 13 || D > kMaxState || !tk) return -1;
+  if (tk->task < 0 || tk->task > 3 || (tk->task != 0 && (tk->lookahead < 1 || tk->lookahead > 16)))
+    return -1;
+  if (tk->episode_steps < 1) return -1;
+  for (int c = 0; c < n_classes; ++c) {
+    const OrVehicle& v = classes[c];
+    if (v.n_thr < 1 || v.n_thr > nmax || v.n_thr > kMaxThr) return -1;
+    if (v.thr_tau > 0.0 && 13 + v.n_thr > D) return -1;
+  }
+  const int od = task_obs_dim(*tk);
+  const double dtc = S * dt;
+  const double dl = tk->lookahead_dt > 0.0 ? tk->lookahead_dt : dtc;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(resolve_threads(nthreads))
+  for (int64_t e = 0; e < E; ++e) {
+    const int cls = env_class ? env_class[e] : 0;
+    double m23[23], c[3], o[6 * 16 + 6];
+    if (mult)
+      for (int k = 0; k < 23; ++k) m23[k] = mult[(size_t)k * E + e];
+    Body<double> b = make_body<double>(classes[cls], mult ? m23 : nullptr, nullptr);
+    const int Dc = b.state_dim();
+    for (int i = 0; i < 3; ++i) c[i] = center[(size_t)i * E + e];
+    const double ph = phase[e], yw = yaw ? yaw[e] : 0.0;
+    double x[kMaxState];
+    for (int i = 0; i < Dc; ++i) x[i] = x0[(size_t)i * E + e];
+    int32_t k = k0 ? k0[e] : 0;
+    auto put_obs = [&](int slot) {
+      if (!obs) return;
+      task_observe(*tk, x, c, ph, yw, k * dtc, dl, o);
+      for (int i = 0; i < od; ++i) obs[((size_t)slot * od + i) * E + e] = o[i];
+    };
+    put_obs(0);
+    for (int t = 0; t < T; ++t) {
+      double a[kMaxThr];
+      for (int i = 0; i < b.n_thr; ++i) a[i] = act[((size_t)t * nmax + i) * E + e];
+      control_step(b, x, a, S, dt);
+      k += 1;
+      bool finite = true;
+      for (int i = 0; i < Dc; ++i) finite = finite && std::isfinite(x[i]);
+      const double ee = task_error(*tk, x, c, ph, yw, k * dtc);
+      const bool term = !finite || (tk->max_error > 0.0 && !(ee <= tk->max_error));
+      const int32_t d = term ? 1 : (k >= tk->episode_steps ? 2 : 0);
+      if (err) err[(size_t)t * E + e] = ee;
+      if (done) done[(size_t)t * E + e] = d;
+      if (d) {
+        for (int i = 0; i < Dc; ++i)
+          x[i] = reset_state ? reset_state[(size_t)i * E + e] : (i == 3 ? 1.0 : 0.0);
+        k = 0;
+        if (reset_mult) {
+          for (int j = 0; j < 23; ++j) m23[j] = reset_mult[(size_t)j * E + e];
+          b = make_body<double>(classes[cls], m23, nullptr);
+        }
+      }
+      put_obs(t + 1);
+    }
+    if (xT)
+      for (int i = 0; i < D; ++i) xT[(size_t)i * E + e] = i < Dc ? x[i] : 0.0;
+    if (kT) kT[e] = k;
   }
   return 0;
 }

@@ -36,6 +36,35 @@ class OrVehicle(ctypes.Structure):
     ]
 
 
+class OrTask(ctypes.Structure):
+    _fields_ = [
+        ("task", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+        ("radius", ctypes.c_double), ("omega", ctypes.c_double),
+        ("climb_rate", ctypes.c_double), ("lookahead_dt", ctypes.c_double),
+        ("episode_steps", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("max_error", ctypes.c_double),
+    ]
+
+
+TASKS = {"station": 0, "circle": 1, "helix": 2, "lemniscate": 3}
+
+
+def task_struct(task):
+    """Fill the oracle's task struct from a dict: task (name or 0..3), lookahead, radius,
+    omega, climb_rate, lookahead_dt, episode_steps, max_error."""
+    t = OrTask()
+    kind = task["task"]
+    t.task = TASKS[kind] if isinstance(kind, str) else int(kind)
+    t.lookahead = int(task.get("lookahead", 1))
+    t.radius = float(task.get("radius", 0.0))
+    t.omega = float(task.get("omega", 0.0))
+    t.climb_rate = float(task.get("climb_rate", 0.0))
+    t.lookahead_dt = float(task.get("lookahead_dt", 0.0))
+    t.episode_steps = int(task.get("episode_steps", 1 << 30))
+    t.max_error = float(task.get("max_error", 0.0))
+    return t
+
+
 def build(force=False):
     """Compile the oracle with g++ (OpenMP, FP64, no fast-math)."""
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
@@ -80,9 +109,21 @@ def lib():
                                          _dp, _dp, ctypes.c_int]
         L.or_jvp.argtypes = [vp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                              ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
+        tp = ctypes.POINTER(OrTask)
+        L.or_task_reference.argtypes = [tp, _dp, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, _dp, _dp]
+        L.or_euler_zyx.argtypes = [_dp, _dp]
+        L.or_task_obs_dim.argtypes = [tp]
+        L.or_task_observe.argtypes = [tp, ctypes.c_int64, _dp, ctypes.c_int, _dp, _dp, _dp, _ip,
+                                      ctypes.c_double, _dp]
+        L.or_task_rollout.argtypes = [vp, ctypes.c_int, _ip, ctypes.c_int64, _dp, _dp,
+                                      ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_double, tp, _dp, _dp, _dp, _ip, _dp, _dp, _dp,
+                                      _dp, _ip, _dp, _ip, ctypes.c_int]
         for name in ("or_alloc", "or_mass_matrix", "or_coriolis_matrix", "or_restoring",
                      "or_rotation", "or_rhs", "or_rollout", "or_track_loss",
-                     "or_track_loss_grad", "or_jvp"):
+                     "or_track_loss_grad", "or_jvp", "or_task_reference", "or_euler_zyx",
+                     "or_task_obs_dim", "or_task_observe", "or_task_rollout"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -262,3 +303,81 @@ def jvp(preset, x0, act, n_substeps, dt, mult=None, dact=None, dtheta=None, dx0=
     if rc != 0:
         raise ValueError("or_jvp rejected its arguments")
     return traj, dtraj
+
+
+# -- tasks of Sec. III ---------------------------------------------------------------------
+
+def _i32(a):
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def task_reference(task, center, phase, yaw, t):
+    """Reference point (3,) and heading of one env at episode time t."""
+    pr = np.zeros(3)
+    psi = ctypes.c_double()
+    c = _f64(center)
+    rc = lib().or_task_reference(ctypes.byref(task_struct(task)), _ptr(c), float(phase),
+                                 float(yaw), float(t), _ptr(pr), ctypes.byref(psi))
+    if rc != 0:
+        raise ValueError("or_task_reference rejected its arguments")
+    return pr, psi.value
+
+
+def euler_zyx(q):
+    rpy = np.zeros(3)
+    lib().or_euler_zyx(_ptr(_f64(q)), _ptr(rpy))
+    return rpy
+
+
+def task_obs_dim(task):
+    return lib().or_task_obs_dim(ctypes.byref(task_struct(task)))
+
+
+def task_observe(task, x, center, phase, yaw, k, dt_ctrl):
+    """Observations [obs_dim][E] of states x [D][E] at episode steps k [E]."""
+    x = _f64(x)
+    D, E = x.shape
+    obs = np.zeros((task_obs_dim(task), E))
+    c, ph, yw, kk = _f64(center), _f64(phase), _f64(yaw), _i32(k)
+    rc = lib().or_task_observe(ctypes.byref(task_struct(task)), E, _ptr(x), D, _ptr(c), _ptr(ph),
+                               _ptr(yw), kk.ctypes.data_as(_ip) if kk is not None else None,
+                               float(dt_ctrl), _ptr(obs))
+    if rc != 0:
+        raise ValueError("or_task_observe rejected its arguments")
+    return obs
+
+
+def task_rollout(presets, task, x0, act, n_substeps, dt, center, phase, yaw=None, env_class=None,
+                 mult=None, k0=None, reset_state=None, reset_mult=None, nthreads=0):
+    """T Gym-style steps with the task epilogue and automatic reset; returns dict with
+    'obs' [T+1][obs_dim][E], 'err' [T][E], 'done' [T][E], 'x' [D][E], 'k' [E]."""
+    if isinstance(presets, dict):
+        presets = [presets]
+    x0 = _f64(x0)
+    act = _f64(act)
+    D, E = x0.shape
+    T, nmax, E2 = act.shape
+    assert E2 == E
+    vs = (OrVehicle * len(presets))(*[vehicle(p) for p in presets])
+    ec = _i32(env_class)
+    tk = task_struct(task)
+    od = lib().or_task_obs_dim(ctypes.byref(tk))
+    obs = np.zeros((T + 1, od, E))
+    err = np.zeros((T, E))
+    done = np.zeros((T, E), np.int32)
+    xT = np.zeros((D, E))
+    kT = np.zeros(E, np.int32)
+    k0a = _i32(k0)
+    m, c, ph, yw, rs, rm = (_f64(mult), _f64(center), _f64(phase), _f64(yaw), _f64(reset_state),
+                            _f64(reset_mult))
+    rc = lib().or_task_rollout(vs, len(presets), ec.ctypes.data_as(_ip) if ec is not None else None,
+                               E, _ptr(m), _ptr(x0), D, _ptr(act), nmax, T, int(n_substeps),
+                               float(dt), ctypes.byref(tk), _ptr(c), _ptr(ph), _ptr(yw),
+                               k0a.ctypes.data_as(_ip) if k0a is not None else None, _ptr(rs),
+                               _ptr(rm), _ptr(obs), _ptr(err), done.ctypes.data_as(_ip), _ptr(xT),
+                               kT.ctypes.data_as(_ip), int(nthreads))
+    if rc != 0:
+        raise ValueError("or_task_rollout rejected its arguments")
+    return {"obs": obs, "err": err, "done": done, "x": xT, "k": kT}

@@ -175,6 +175,75 @@ mg_status mg_get_params(mg_sim* sim, float* out, int32_t out_on_device);
 /* Waits for the sim's stream; returns MG_ERR_DEVICE if queued work failed. */
 mg_status mg_synchronize(mg_sim* sim);
 
+/* ---- Gym-style tasks (Sec. III) ------------------------------------------------------
+ * The four control tasks of Sec. III as vectorised environments: station
+ * keeping and circle, helix and lemniscate tracking.  A task step is one
+ * control step (as mg_step with n_ctrl = 1) followed, in the same launch, by
+ * the task epilogue: the episode counter advances, the position error of
+ * Eq. (4) is taken against the reference at the new episode time, an episode
+ * ends terminated (done 1: non-finite state, or error above max_error > 0) or
+ * truncated (done 2: episode_steps reached) and restarts at once, and the
+ * observation of Eq. (2) is written.  The epilogue computes in FP64 from the
+ * FP32 state.
+ *
+ * mg_task
+ *   task           MG_TASK_STATION / CIRCLE / HELIX / LEMNISCATE
+ *   lookahead      m, reference points in a tracking observation (1..16)
+ *   radius         R (m); omega: rate of the curve parameter s = omega t + phase (rad/s)
+ *   climb_rate     helix vertical rate (m/s along NED z)
+ *   lookahead_dt   time between look-ahead points (s); <= 0: one control step
+ *   episode_steps  control steps per episode (>= 1)
+ *   max_error      error bound (m) that terminates an episode; 0: none
+ * Reference points (t: seconds since the env's episode began):
+ *   station    the env's centre; heading: its target yaw
+ *   circle     c + R (cos s, sin s, 0); helix: the circle + (0, 0, climb_rate t)
+ *   lemniscate c + R (cos s, sin s cos s, 0) / (1 + sin^2 s)  (Bernoulli)
+ *   the reference attitude is level, headed along the horizontal reference velocity
+ * Observation (caller layout [obs_dim][E]):
+ *   station  [p - c, roll, pitch, wrap(yaw - target yaw), nu]          12 rows
+ *   tracking for i = 1..m: [p - p_r(t + i dl), roll, pitch,
+ *            wrap(yaw - heading_r(t + i dl))], then nu                  6 m + 6 rows
+ *   NED position errors, ZYX Euler angles, angles in (-pi, pi].
+ */
+#define MG_TASK_STATION 0
+#define MG_TASK_CIRCLE 1
+#define MG_TASK_HELIX 2
+#define MG_TASK_LEMNISCATE 3
+#define MG_MAX_LOOKAHEAD 16
+
+typedef struct {
+  int32_t task, lookahead;
+  double radius, omega, climb_rate, lookahead_dt;
+  int32_t episode_steps, reserved;
+  double max_error;
+} mg_task;
+
+/* Sets the task and each env's centre (device [3][E]), curve phase (device
+ * [E]) and target yaw (device [E], or NULL: 0); every episode counter starts
+ * at 0.  mg_reset also zeroes the counters of the envs whose state it
+ * resets.  Copies the inputs (stream-ordered). */
+mg_status mg_task_configure(mg_sim* sim, const mg_task* task, const float* center,
+                            const float* phase, const float* yaw);
+/* Observation rows: 12 (station keeping), 6 m + 6 (tracking); 0 if no task. */
+int32_t mg_task_obs_dim(const mg_sim* sim);
+/* Writes the observation of the current states to device obs [obs_dim][E]. */
+mg_status mg_task_observe(mg_sim* sim, float* obs);
+/* One Gym step of every env.
+ *   actions      device [N_max][E] throttles of this control step
+ *   obs          device [obs_dim][E] (written): after the step, or of the new
+ *                episode where one ended
+ *   err          device [E] position error of Eq. (4) after the step, or NULL
+ *   done         device int32 [E]: 0 running, 1 terminated, 2 truncated, or NULL
+ *   reset_state  device [D][E] states an ended episode restarts from, or NULL
+ *                (at rest at the origin, identity attitude, no thrust)
+ *   reset_mult   device [23][E] parameter multipliers an ended episode
+ *                restarts with (refactorised as by mg_reset), or NULL (kept) */
+mg_status mg_task_step(mg_sim* sim, const float* actions, float* obs, float* err, int32_t* done,
+                       const float* reset_state, const float* reset_mult);
+/* Copies the episode counters (control steps since each env's episode began)
+ * to device int32 out [E]. */
+mg_status mg_task_counters(mg_sim* sim, int32_t* out);
+
 /* ---- discrete adjoint of a rollout -------------------------------------------------
  * The reverse mode of the exact discrete map mg_step computes (RK4 stages,
  * quaternion renormalisation, thruster lag and clamp), for gradient-based use

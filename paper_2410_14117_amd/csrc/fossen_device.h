@@ -135,6 +135,32 @@ __device__ __forceinline__ void derive_constants(const double (&prm)[kNumParams]
   for (int i = 0; i < kNumDerived; ++i) out[i] = spd ? (float)dv[i] : __builtin_nanf("");
 }
 
+// One env's parameters: the class nominal values times the multipliers
+// in[i * stride] (absolute values if `absolute`; nominal if in is NULL),
+// each rounded once to FP32 and stored, and the factorisation derived from
+// the stored FP32 values (so a sim restored from its parameters reproduces
+// the original bitwise).
+__device__ __forceinline__ void set_env_params(const ClassNominal& nom, const float* in,
+                                               int64_t stride, bool absolute, float* params,
+                                               float* derived, int64_t Ep, int64_t j) {
+  double prm[kNumParams];
+#pragma unroll
+  for (int i = 0; i < kNumParams; ++i) {
+    double pi = nom.p[i];
+    if (in) {
+      const double v = in[i * stride];
+      pi = absolute ? v : pi * v;
+    }
+    const float pf = (float)pi;
+    prm[i] = (double)pf;
+    params[i * Ep + j] = pf;
+  }
+  float dvf[kNumDerived];
+  derive_constants(prm, nom.zg, nom.zb, dvf);
+#pragma unroll
+  for (int i = 0; i < kNumDerived; ++i) derived[i * Ep + j] = dvf[i];
+}
+
 template <int N, bool LAG>
 struct Dims {
   static constexpr int D = 13 + (LAG ? N : 0);

@@ -196,25 +196,9 @@ __global__ void __launch_bounds__(256) k_reset(const ResetArgs a) {
   if (id < 0 || id >= a.E) return;
   const int64_t j = a.iperm ? (int64_t)a.iperm[id] : id;
   const ClassNominal& nom = a.nominal[a.class_of[j]];
-
-  double prm[kNumParams];
-#pragma unroll
-  for (int i = 0; i < kNumParams; ++i) {
-    double pi = nom.p[i];
-    if (a.param_in) {
-      const double in = a.param_in[i * a.n + k];
-      pi = a.param_absolute ? in : pi * in;
-    }
-    // the stored FP32 value alone determines everything derived from it, so a
-    // sim restored from mg_get_params reproduces the original bitwise
-    const float pf = (float)pi;
-    prm[i] = (double)pf;
-    a.params[i * a.Ep + j] = pf;
-  }
-  float dvf[kNumDerived];
-  derive_constants(prm, nom.zg, nom.zb, dvf);
-#pragma unroll
-  for (int i = 0; i < kNumDerived; ++i) a.derived[i * a.Ep + j] = dvf[i];
+  set_env_params(nom, a.param_in ? a.param_in + k : nullptr, a.n, a.param_absolute != 0,
+                 a.params, a.derived, a.Ep, j);
+  if (a.write_state && a.task_k) a.task_k[j] = 0;
 
   if (a.write_state) {
     const int Dc = 13 + (nom.lag ? nom.n_thr : 0);

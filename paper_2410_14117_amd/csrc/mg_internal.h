@@ -94,6 +94,35 @@ struct ResetArgs {
   const float* param_in;       // [23][n] or NULL (nominal)
   int32_t param_absolute;      // param_in holds absolute values (else multipliers)
   int32_t write_state;         // 0: keep the state
+  int32_t* task_k;             // internal [Ep] episode counters zeroed with the state, or NULL
+};
+
+// Gym-style task of Sec. III (wave-uniform, by value): kind, look-ahead
+// count m, episode length L, curve radius, parameter rate, helix vertical
+// rate, look-ahead spacing and control-step duration (s), error bound (m).
+struct TaskConst {
+  int32_t task, m, L, pad_;
+  double R, omega, climb, dl, dtc, emax;
+};
+
+struct TaskArgs {
+  float* state;                // internal [D][Ep]
+  float* params;               // internal [23][Ep]
+  float* derived;              // internal [kNumDerived][Ep]
+  const float* task_f;         // internal [5][Ep]: centre x, y, z, curve phase, target yaw
+  int32_t* task_k;             // internal [Ep] control steps since the episode began
+  int64_t Ep, E;
+  const int32_t* perm;         // internal -> caller, NULL = identity
+  int64_t seg_start, seg_len;
+  const ClassNominal* nominal; // device, this class's entry
+  const float* actions;        // caller [n_max][E], or NULL: observe only
+  int32_t n_max, D, substeps;
+  float dt;
+  float* obs;                  // caller [obs_dim][E]
+  float* err;                  // caller [E] or NULL
+  int32_t* done;               // caller [E] or NULL
+  const float* reset_state;    // caller [D][E] or NULL (rest at the origin)
+  const float* reset_mult;     // caller [23][E] or NULL (parameters kept)
 };
 
 struct AdjArgs {
@@ -170,6 +199,7 @@ hipError_t launch_step(const ClassConst& cc, const StepArgs& a, hipStream_t s);
 hipError_t launch_stats_finalize(const double* partials, int32_t nblk, int32_t n_ctrl,
                                  double* stats, hipStream_t s);
 hipError_t launch_reset(const ResetArgs& a, hipStream_t s);
+hipError_t launch_task(const ClassConst& cc, const TaskConst& tc, const TaskArgs& a, hipStream_t s);
 // out[r][perm[j]] = in[r][j] for rows r < rows (internal -> caller order)
 hipError_t launch_gather_out(const float* in, int64_t Ep, float* out, int64_t E, int32_t rows,
                              const int32_t* perm, int64_t n_internal, hipStream_t s);

@@ -65,6 +65,11 @@ struct mg_sim {
   float* segbuf = nullptr;     // adjoint recomputation scratch
   size_t segbuf_cap = 0;       // floats
   std::map<GraphKey, hipGraphExec_t> graphs;
+  // Gym-style task (mg_task_configure)
+  bool task_on = false;
+  TaskConst task{};
+  float* task_f = nullptr;     // [5][Ep] centre, curve phase, target yaw
+  int32_t* task_k = nullptr;   // [Ep] control steps since each env's episode began
 };
 
 // Class constants the step kernels read from scalar registers.
@@ -291,6 +296,7 @@ mg_status reset_impl(mg_sim* s, const int64_t* ids, int64_t n, const float* stat
   r.param_in = param_in;
   r.param_absolute = absolute;
   r.write_state = write_state;
+  r.task_k = s->task_k;
   MG_HIP(s, launch_reset(r, s->stream));
   return MG_OK;
 }
@@ -348,6 +354,59 @@ AdjArgs adj_args(mg_sim* s, const float* actions, int32_t T, int32_t K) {
   a.ckpt_every = K;
   a.dt = (float)s->dt;
   return a;
+}
+
+// internal [rows][Ep] <- caller [rows][E] (device)
+mg_status copy_in(mg_sim* s, const float* src, int32_t rows, float* dst) {
+  if (!s->perm) {
+    MG_HIP(s, hipMemcpy2DAsync(dst, s->Ep * sizeof(float), src, s->E * sizeof(float),
+                               s->E * sizeof(float), rows, hipMemcpyDeviceToDevice, s->stream));
+  } else {
+    MG_HIP(s, launch_scatter_in(src, s->E, dst, s->Ep, rows, s->perm, s->Ep, s->stream));
+  }
+  return MG_OK;
+}
+
+// One task launch per class (forked / joined like the step): a Gym step when
+// actions is given, else the observation alone.
+mg_status enqueue_task(mg_sim* s, const float* actions, float* obs, float* err, int32_t* done,
+                       const float* reset_state, const float* reset_mult) {
+  hipStream_t st = s->stream;
+  TaskArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.state = s->state;
+  a.params = s->params;
+  a.derived = s->derived;
+  a.task_f = s->task_f;
+  a.task_k = s->task_k;
+  a.Ep = s->Ep;
+  a.E = s->E;
+  a.perm = s->perm;
+  a.actions = actions;
+  a.n_max = s->n_max;
+  a.D = s->D;
+  a.substeps = s->substeps;
+  a.dt = (float)s->dt;
+  a.obs = obs;
+  a.err = err;
+  a.done = done;
+  a.reset_state = reset_state;
+  a.reset_mult = reset_mult;
+  for (int k = 1; k < s->n_classes; ++k) {
+    MG_HIP(s, hipEventRecord(s->ev_fork[k - 1], st));
+    MG_HIP(s, hipStreamWaitEvent(s->aux[k - 1], s->ev_fork[k - 1], 0));
+  }
+  for (int k = 0; k < s->n_classes; ++k) {
+    a.seg_start = s->seg_start[k];
+    a.seg_len = s->seg_len[k];
+    a.nominal = s->nominal_dev + k;
+    MG_HIP(s, launch_task(s->cc[k], s->task, a, k == 0 ? st : s->aux[k - 1]));
+  }
+  for (int k = 1; k < s->n_classes; ++k) {
+    MG_HIP(s, hipEventRecord(s->ev_join[k - 1], s->aux[k - 1]));
+    MG_HIP(s, hipStreamWaitEvent(st, s->ev_join[k - 1], 0));
+  }
+  return MG_OK;
 }
 
 }  // namespace
@@ -519,7 +578,7 @@ void mg_destroy(mg_sim* s) {
     for (hipEvent_t e : s->ev_fork) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->ev_join) (void)hipEventDestroy(e);
     void* bufs[] = {s->state, s->params, s->derived, s->perm, s->iperm, s->class_of,
-                    s->nominal_dev, s->partials, s->staging, s->segbuf};
+                    s->nominal_dev, s->partials, s->staging, s->segbuf, s->task_f, s->task_k};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     (void)hipGetLastError();
@@ -577,6 +636,85 @@ mg_status mg_set_state(mg_sim* s, const float* state) {
 mg_status mg_step(mg_sim* s, const float* actions, int32_t n_ctrl, const float* targets,
                   float* traj, double* stats) {
   return step_common(s, actions, n_ctrl, targets, traj, stats, false);
+}
+
+mg_status mg_task_configure(mg_sim* s, const mg_task* task, const float* center,
+                            const float* phase, const float* yaw) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!task || !center || !phase) return fail(s, MG_ERR_INVALID, "task, center and phase are required");
+  if (task->task < MG_TASK_STATION || task->task > MG_TASK_LEMNISCATE)
+    return fail(s, MG_ERR_INVALID, "unknown task");
+  if (task->task != MG_TASK_STATION && (task->lookahead < 1 || task->lookahead > MG_MAX_LOOKAHEAD))
+    return fail(s, MG_ERR_INVALID, "lookahead outside 1..MG_MAX_LOOKAHEAD");
+  if (task->episode_steps < 1) return fail(s, MG_ERR_INVALID, "episode_steps must be >= 1");
+  const double vals[] = {task->radius, task->omega, task->climb_rate, task->lookahead_dt,
+                         task->max_error};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(s, MG_ERR_INVALID, "non-finite task parameter");
+  if (task->max_error < 0.0) return fail(s, MG_ERR_INVALID, "max_error must be >= 0");
+  DeviceGuard g(s->device);
+  if (!s->task_f) {
+    if (hipMalloc(&s->task_f, (size_t)5 * s->Ep * sizeof(float)) != hipSuccess ||
+        hipMalloc(&s->task_k, (size_t)s->Ep * sizeof(int32_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(s, MG_ERR_OOM, "task buffers");
+    }
+    MG_HIP(s, hipMemsetAsync(s->task_f, 0, (size_t)5 * s->Ep * sizeof(float), s->stream));
+  }
+  if ((st = copy_in(s, center, 3, s->task_f))) return st;
+  if ((st = copy_in(s, phase, 1, s->task_f + 3 * s->Ep))) return st;
+  if (yaw) {
+    if ((st = copy_in(s, yaw, 1, s->task_f + 4 * s->Ep))) return st;
+  } else {
+    MG_HIP(s, hipMemsetAsync(s->task_f + 4 * s->Ep, 0, (size_t)s->Ep * sizeof(float), s->stream));
+  }
+  MG_HIP(s, hipMemsetAsync(s->task_k, 0, (size_t)s->Ep * sizeof(int32_t), s->stream));
+  TaskConst& tc = s->task;
+  tc.task = task->task;
+  tc.m = task->task == MG_TASK_STATION ? 1 : task->lookahead;
+  tc.L = task->episode_steps;
+  tc.R = task->radius;
+  tc.omega = task->omega;
+  tc.climb = task->climb_rate;
+  tc.dtc = s->dt * s->substeps;
+  tc.dl = task->lookahead_dt > 0.0 ? task->lookahead_dt : tc.dtc;
+  tc.emax = task->max_error;
+  s->task_on = true;
+  return MG_OK;
+}
+
+int32_t mg_task_obs_dim(const mg_sim* s) {
+  if (!s || !s->task_on) return 0;
+  return s->task.task == MG_TASK_STATION ? 12 : 6 * s->task.m + 6;
+}
+
+mg_status mg_task_observe(mg_sim* s, float* obs) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!s->task_on) return fail(s, MG_ERR_INVALID, "no task configured");
+  if (!obs) return fail(s, MG_ERR_INVALID, "obs is NULL");
+  DeviceGuard g(s->device);
+  return enqueue_task(s, nullptr, obs, nullptr, nullptr, nullptr, nullptr);
+}
+
+mg_status mg_task_step(mg_sim* s, const float* actions, float* obs, float* err, int32_t* done,
+                       const float* reset_state, const float* reset_mult) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!s->task_on) return fail(s, MG_ERR_INVALID, "no task configured");
+  if (!actions || !obs) return fail(s, MG_ERR_INVALID, "actions and obs are required");
+  DeviceGuard g(s->device);
+  return enqueue_task(s, actions, obs, err, done, reset_state, reset_mult);
+}
+
+mg_status mg_task_counters(mg_sim* s, int32_t* out) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!s->task_on) return fail(s, MG_ERR_INVALID, "no task configured");
+  DeviceGuard g(s->device);
+  // the layout copy moves 32-bit words unchanged, so it serves int32 rows too
+  return copy_out(s, reinterpret_cast<const float*>(s->task_k), 1, reinterpret_cast<float*>(out), 1);
 }
 
 mg_status mg_step_plain(mg_sim* s, const float* actions, int32_t n_ctrl, const float* targets,

@@ -59,6 +59,35 @@ class MgServerConfig(ctypes.Structure):
     ]
 
 
+class MgTask(ctypes.Structure):
+    _fields_ = [
+        ("task", ctypes.c_int32), ("lookahead", ctypes.c_int32),
+        ("radius", ctypes.c_double), ("omega", ctypes.c_double),
+        ("climb_rate", ctypes.c_double), ("lookahead_dt", ctypes.c_double),
+        ("episode_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("max_error", ctypes.c_double),
+    ]
+
+
+TASKS = {"station": 0, "circle": 1, "helix": 2, "lemniscate": 3}
+
+
+def task_struct(task):
+    """mg_task from a dict: task (name or 0..3), lookahead, radius, omega, climb_rate,
+    lookahead_dt, episode_steps, max_error."""
+    t = MgTask()
+    kind = task["task"]
+    t.task = TASKS[kind] if isinstance(kind, str) else int(kind)
+    t.lookahead = int(task.get("lookahead", 1))
+    t.radius = float(task.get("radius", 0.0))
+    t.omega = float(task.get("omega", 0.0))
+    t.climb_rate = float(task.get("climb_rate", 0.0))
+    t.lookahead_dt = float(task.get("lookahead_dt", 0.0))
+    t.episode_steps = int(task.get("episode_steps", 1 << 30))
+    t.max_error = float(task.get("max_error", 0.0))
+    return t
+
+
 class MgRequest(ctypes.Structure):
     _fields_ = [
         ("n_envs", ctypes.c_int64), ("n_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
@@ -104,6 +133,11 @@ _SIGS = {
     "mg_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(MgServerStats)]),
     "mg_server_last_error": (ctypes.c_char_p, [_vp]),
     "mg_server_destroy": (None, [_vp]),
+    "mg_task_configure": (ctypes.c_int32, [_vp, ctypes.POINTER(MgTask), _vp, _vp, _vp]),
+    "mg_task_obs_dim": (ctypes.c_int32, [_vp]),
+    "mg_task_observe": (ctypes.c_int32, [_vp, _vp]),
+    "mg_task_step": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mg_task_counters": (ctypes.c_int32, [_vp, _vp]),
     "mg_adj_forward": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
     "mg_adj_backward": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                          _vp, _vp]),
@@ -265,6 +299,58 @@ class Sim:
         tr = _ptr(traj, torch.float32, (n_ctrl, D, E), "traj")
         stt = _ptr(stats, torch.float64, (n_ctrl, NUM_STATS), "stats")
         return a, tg, tr, stt
+
+    # -- Gym-style tasks ---------------------------------------------------------------------
+    def task_configure(self, task, center, phase, yaw=None):
+        """task: dict (see task_struct); center [3][E], phase [E], yaw [E] device tensors."""
+        import torch
+        E = self.n_envs
+        self._task = task_struct(task)
+        self._bind_stream()
+        self._check(lib().mg_task_configure(
+            self._h, ctypes.byref(self._task), _ptr(center, torch.float32, (3, E), "center"),
+            _ptr(phase, torch.float32, (E,), "phase"), _ptr(yaw, torch.float32, (E,), "yaw")))
+        self.obs_dim = lib().mg_task_obs_dim(self._h)
+
+    def task_observe(self, obs=None):
+        import torch
+        if obs is None:
+            obs = torch.empty((self.obs_dim, self.n_envs), dtype=torch.float32,
+                              device=f"cuda:{self.device}")
+        p = _ptr(obs, torch.float32, (self.obs_dim, self.n_envs), "obs")
+        self._bind_stream()
+        self._check(lib().mg_task_observe(self._h, p))
+        return obs
+
+    def task_step(self, actions, obs=None, err=None, done=None, reset_state=None,
+                  reset_mult=None):
+        """actions [N_max][E]; returns (obs [obs_dim][E], err [E], done [E] int32)."""
+        import torch
+        E, dev = self.n_envs, f"cuda:{self.device}"
+        if obs is None:
+            obs = torch.empty((self.obs_dim, E), dtype=torch.float32, device=dev)
+        if err is None:
+            err = torch.empty((E,), dtype=torch.float32, device=dev)
+        if done is None:
+            done = torch.empty((E,), dtype=torch.int32, device=dev)
+        args = (_ptr(actions, torch.float32, (self.action_dim, E), "actions"),
+                _ptr(obs, torch.float32, (self.obs_dim, E), "obs"),
+                _ptr(err, torch.float32, (E,), "err"),
+                _ptr(done, torch.int32, (E,), "done"),
+                _ptr(reset_state, torch.float32, (self.state_dim, E), "reset_state"),
+                _ptr(reset_mult, torch.float32, (NUM_PARAMS, E), "reset_mult"))
+        self._bind_stream()
+        self._check(lib().mg_task_step(self._h, *args))
+        return obs, err, done
+
+    def task_counters(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.n_envs,), dtype=torch.int32, device=f"cuda:{self.device}")
+        p = _ptr(out, torch.int32, (self.n_envs,), "out")
+        self._bind_stream()
+        self._check(lib().mg_task_counters(self._h, p))
+        return out
 
     def step(self, actions, targets=None, traj=None, stats=None, plain=False):
         """actions [n_ctrl][N_max][E]: n_ctrl control steps fused in one launch per class."""

@@ -265,6 +265,48 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
             "submit_lag_p99_ms": float(np.percentile(lags, 99) / 1e6)}
 
 
+def bench_task(torch, sim, act, x0, n_steps=60):
+    """Gym-style circle tracking on the benchmark's envs: 4 look-ahead points in the
+    observation (30 rows), episodes of 100 control steps with automatic reset, the error of
+    Eq. (4) and the done flags; n_steps task steps (one launch per class each, issued from
+    Python) against as many single-control-step mg_step calls issued the same way."""
+    E, dev = sim.n_envs, x0.device
+    g = torch.Generator(device="cpu").manual_seed(7007)
+    center = torch.zeros((3, E), dtype=torch.float32, device=dev)
+    phase = (torch.rand(E, generator=g) * 6.283185307179586).to(dev)
+    task = {"task": "circle", "lookahead": 4, "radius": 2.0, "omega": 0.5, "episode_steps": 100}
+    sim.reset(state=x0)
+    sim.task_configure(task, center, phase)
+    obs = torch.empty((sim.obs_dim, E), dtype=torch.float32, device=dev)
+    err = torch.empty((E,), dtype=torch.float32, device=dev)
+    done = torch.empty((E,), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for t in range(3):
+            fn(t)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for t in range(n_steps):
+            fn(t % act.shape[0])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n_steps
+
+    task_ms = timed(lambda t: sim.task_step(act[t], obs, err, done, reset_state=x0))
+    sim.reset(state=x0)
+    step_ms = timed(lambda t: sim.step(act[t:t + 1]))
+    S = sim.substeps
+    return {"workload": f"{E} envs (the benchmark's mix), circle tracking, m = 4 look-ahead "
+                        "points, episodes of 100 control steps, automatic reset",
+            "obs_rows": sim.obs_dim, "ms_per_task_step": task_ms,
+            "ms_per_plain_control_step_call": step_ms,
+            "epilogue_overhead": task_ms / step_ms - 1.0,
+            "env_task_steps_per_s": E / (task_ms * 1e-3),
+            "env_steps_per_s": E * S / (task_ms * 1e-3)}
+
+
 def summarise_profile(root):
     """Summary of rocprofv3 CSV output under `root` (host-only, no GPU): per-kernel launch
     statistics from kernel_stats.csv; for the k_step launches of a kernel trace the union of
@@ -329,6 +371,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-task", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one device copy of 1 GiB (read 1 GiB, write 1 GiB) whose "
@@ -456,6 +499,8 @@ def main():
             "frac_hbm": bytes_rollout / (plain_ms * 1e-3) / PEAK_HBM,
             "speedup_fused_vs_plain": plain_ms / fused_ms,
         }
+    if not args.no_task:
+        out["task_epilogue"] = bench_task(torch, sim, act, x0)
     sim.close()
     del act
     torch.cuda.empty_cache()

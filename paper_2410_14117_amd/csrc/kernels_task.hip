@@ -9,73 +9,103 @@ namespace mg {
 
 namespace {
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kPi = 3.1415926535897932384626433832795;
 
-// Angle in (-pi, pi].
-__device__ __forceinline__ double wrap_pi(double a) {
-  double r = a - kTwoPi * rint(a / kTwoPi);
-  if (r <= -kPi) r += kTwoPi;
-  if (r > kPi) r -= kTwoPi;
-  return r;
-}
-
-// Reference point and heading at episode time t.  Curve parameter
-// s = omega t + phase; the heading follows the horizontal reference velocity,
-// which is omega (-sin s, cos s) R for the circle and the helix and, for the
-// lemniscate of Bernoulli R (cos s, sin s cos s) / (1 + sin^2 s),
-// omega R (-sin s (3 - sin^2 s), 1 - 3 sin^2 s) / (1 + sin^2 s)^2.
-__device__ __forceinline__ void reference(const TaskConst& tc, const double (&c)[3], double phase,
-                                          double yaw, double t, double (&pr)[3], double& psi) {
+// Reference point p_r and the horizontal direction (vx, vy) of the reference
+// heading, given sin and cos of the curve parameter s = omega t + phase.  For
+// the circle and the helix the reference velocity is omega R (-sin s, cos s);
+// for the lemniscate of Bernoulli R (cos s, sin s cos s) / (1 + sin^2 s) it is
+// omega R (-sin s (3 - sin^2 s), 1 - 3 sin^2 s) / (1 + sin^2 s)^2 (the positive
+// factor R / (1 + sin^2 s)^2 drops out of the direction).  Station keeping:
+// the centre, headed along the target yaw.
+__device__ __forceinline__ void reference(const TaskConst& tc, const double (&c)[3], double yaw,
+                                          double t, double sn, double cs, double (&pr)[3],
+                                          double& vx, double& vy) {
   if (tc.task == 0) {
     pr[0] = c[0];
     pr[1] = c[1];
     pr[2] = c[2];
-    psi = yaw;
+    float sy, cy;
+    sincosf((float)yaw, &sy, &cy);
+    vx = cy;
+    vy = sy;
     return;
   }
-  double sn, cs;
-  sincos(fma(tc.omega, t, phase), &sn, &cs);
   if (tc.task == 3) {
     const double s2 = sn * sn, inv = 1.0 / (1.0 + s2);
     pr[0] = c[0] + tc.R * cs * inv;
     pr[1] = c[1] + tc.R * sn * cs * inv;
     pr[2] = c[2];
-    psi = atan2(tc.omega * (1.0 - 3.0 * s2), -tc.omega * sn * (3.0 - s2));
+    vx = -tc.omega * sn * (3.0 - s2);
+    vy = tc.omega * (1.0 - 3.0 * s2);
   } else {
     pr[0] = c[0] + tc.R * cs;
     pr[1] = c[1] + tc.R * sn;
     pr[2] = c[2] + (tc.task == 2 ? tc.climb * t : 0.0);
-    psi = atan2(tc.omega * cs, -tc.omega * sn);
+    vx = -tc.omega * sn;
+    vy = tc.omega * cs;
   }
 }
 
-// Writes the observation of Eq. (2) of the state x at episode step k.
+// Writes the observation of Eq. (2) of the state x at episode step k, given
+// sin and cos of the curve parameter at that time.  The heading error
+// wrap(yaw - yaw_r) is the signed angle from the reference direction (vx, vy)
+// to the body's horizontal heading h = R(q) e1 (parallel to (cos yaw, sin yaw)
+// while |pitch| < 90 deg), one atan2 per point; the curve parameters of the
+// look-ahead points follow one another by the rotation (cos, sin)(omega dl).
 __device__ __forceinline__ void observe(const TaskConst& tc, const float* x, const double (&c)[3],
-                                        double phase, double yaw, int32_t k, float* obs,
+                                        double yaw, int32_t k, double sn, double cs, float* obs,
                                         int64_t E) {
-  const double w = x[3], qx = x[4], qy = x[5], qz = x[6];
-  // ZYX roll, pitch, yaw of the unit quaternion
-  const double roll = atan2(2.0 * (w * qx + qy * qz), 1.0 - 2.0 * (qx * qx + qy * qy));
-  const double sp = fmin(1.0, fmax(-1.0, 2.0 * (w * qy - qz * qx)));
-  const double pitch = asin(sp);
-  const double head = atan2(2.0 * (w * qz + qx * qy), 1.0 - 2.0 * (qy * qy + qz * qz));
+  // ZYX roll and pitch from the third row of R(q): roll = atan2(R32, R33),
+  // pitch = atan2(-R31, |(R32, R33)|) (well conditioned at any pitch, unlike
+  // asin(-R31) near +-90 deg)
+  const float w = x[3], qx = x[4], qy = x[5], qz = x[6];
+  const float r32 = 2.0f * (w * qx + qy * qz), r33 = 1.0f - 2.0f * (qx * qx + qy * qy);
+  const float r31 = 2.0f * (qx * qz - w * qy);
+  float roll = atan2f(r32, r33);
+  if (roll <= -3.14159265f) roll = 3.14159265f;
+  const float pitch = atan2f(-r31, sqrtf(r32 * r32 + r33 * r33));
+  const double hx = 1.0 - 2.0 * ((double)qy * qy + (double)qz * qz);
+  const double hy = 2.0 * ((double)qx * qy + (double)w * qz);
   const double t = k * tc.dtc;
   const int m = tc.task == 0 ? 1 : tc.m;
   for (int i = 0; i < m; ++i) {
-    double pr[3], psi;
-    reference(tc, c, phase, yaw, tc.task == 0 ? t : fma((double)(i + 1), tc.dl, t), pr, psi);
+    const double sn1 = fma(sn, tc.cdl, cs * tc.sdl);
+    cs = fma(cs, tc.cdl, -sn * tc.sdl);
+    sn = sn1;
+    double pr[3], vx, vy;
+    reference(tc, c, yaw, fma((double)(i + 1), tc.dl, t), sn, cs, pr, vx, vy);
+    float herr = atan2f((float)(hy * vx - hx * vy), (float)(hx * vx + hy * vy));
+    if (herr <= -3.14159265f) herr = 3.14159265f;
     float* o = obs + (int64_t)(6 * i) * E;
     o[0] = (float)(x[0] - pr[0]);
     o[E] = (float)(x[1] - pr[1]);
     o[2 * E] = (float)(x[2] - pr[2]);
-    o[3 * E] = (float)wrap_pi(roll);
-    o[4 * E] = (float)wrap_pi(pitch);
-    o[5 * E] = (float)wrap_pi(head - psi);
+    o[3 * E] = roll;
+    o[4 * E] = pitch;
+    o[5 * E] = herr;
   }
   float* o = obs + (int64_t)(6 * m) * E;
 #pragma unroll
   for (int i = 0; i < 6; ++i) o[i * E] = x[7 + i];
+}
+
+// sin and cos of the curve parameter s = omega t + phase: s is formed and
+// reduced to [-pi, pi] in FP64, then evaluated in FP32 (errors ~1e-7, well
+// inside the observation's FP32 output).
+__device__ __forceinline__ void curve_sincos(const TaskConst& tc, double t, double phase,
+                                             double& sn, double& cs) {
+  if (tc.task == 0) {
+    sn = 0.0;
+    cs = 1.0;
+    return;
+  }
+  const double s = fma(tc.omega, t, phase);
+  const double r = s - (2.0 * kPi) * rint(s * (0.5 / kPi));
+  float sf, cf;
+  sincosf((float)r, &sf, &cf);
+  sn = sf;
+  cs = cf;
 }
 
 }  // namespace
@@ -109,12 +139,15 @@ __global__ void __launch_bounds__(kBlock) k_task(const TaskArgs a, const ClassCo
   // occupy registers across them
   const double cen[3] = {a.task_f[j], a.task_f[a.Ep + j], a.task_f[2 * a.Ep + j]};
   const double phase = a.task_f[3 * a.Ep + j], yaw = a.task_f[4 * a.Ep + j];
+  // sin and cos of the curve parameter at the current episode time
+  double sn, cs;
+  curve_sincos(tc, k * tc.dtc, phase, sn, cs);
   if (a.actions) {
     bool finite = true;
 #pragma unroll
     for (int i = 0; i < D; ++i) finite = finite && isfinite(x[i]);
-    double pr[3], psi;
-    reference(tc, cen, phase, yaw, k * tc.dtc, pr, psi);
+    double pr[3], vx, vy;
+    reference(tc, cen, yaw, k * tc.dtc, sn, cs, pr, vx, vy);
     const double dx = x[0] - pr[0], dy = x[1] - pr[1], dz = x[2] - pr[2];
     const double e = sqrt(dx * dx + dy * dy + dz * dz);
     const bool term = !finite || (tc.emax > 0.0 && !(e <= tc.emax));
@@ -126,6 +159,7 @@ __global__ void __launch_bounds__(kBlock) k_task(const TaskArgs a, const ClassCo
       for (int i = 0; i < D; ++i)
         x[i] = a.reset_state ? a.reset_state[i * a.E + c] : (i == 3 ? 1.0f : 0.0f);
       k = 0;
+      curve_sincos(tc, 0.0, phase, sn, cs);
       if (a.reset_mult)
         set_env_params(*a.nominal, a.reset_mult + c, a.E, false, a.params, a.derived, a.Ep, j);
     }
@@ -133,7 +167,7 @@ __global__ void __launch_bounds__(kBlock) k_task(const TaskArgs a, const ClassCo
     for (int i = 0; i < D; ++i) a.state[i * a.Ep + j] = x[i];
     a.task_k[j] = k;
   }
-  observe(tc, x, cen, phase, yaw, k, a.obs + c, a.E);
+  observe(tc, x, cen, yaw, k, sn, cs, a.obs + c, a.E);
 }
 
 template <int N, bool LAG>

@@ -99,10 +99,11 @@ struct ResetArgs {
 
 // Gym-style task of Sec. III (wave-uniform, by value): kind, look-ahead
 // count m, episode length L, curve radius, parameter rate, helix vertical
-// rate, look-ahead spacing and control-step duration (s), error bound (m).
+// rate, look-ahead spacing and control-step duration (s), error bound (m),
+// and cos / sin of the curve-parameter step omega dl between look-ahead points.
 struct TaskConst {
   int32_t task, m, L, pad_;
-  double R, omega, climb, dl, dtc, emax;
+  double R, omega, climb, dl, dtc, emax, cdl, sdl;
 };
 
 struct TaskArgs {

@@ -680,6 +680,8 @@ mg_status mg_task_configure(mg_sim* s, const mg_task* task, const float* center,
   tc.dtc = s->dt * s->substeps;
   tc.dl = task->lookahead_dt > 0.0 ? task->lookahead_dt : tc.dtc;
   tc.emax = task->max_error;
+  tc.cdl = std::cos(tc.omega * tc.dl);
+  tc.sdl = std::sin(tc.omega * tc.dl);
   s->task_on = true;
   return MG_OK;
 }

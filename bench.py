@@ -307,6 +307,78 @@ def bench_task(torch, sim, act, x0, n_steps=60):
             "env_steps_per_s": E * S / (task_ms * 1e-3)}
 
 
+def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16):
+    """Policy in the loop (the sampling side of the paper's PPO setup, Sec. III): BlueROV2
+    Heavy envs on the circle task (m = 4 look-ahead points, 30 observation rows, episodes of
+    100 control steps of 4 x 5 ms, automatic reset); per step an actor and a critic MLP
+    (30-256-128-64, ELU; FP32, random init) read the observation, Gaussian actions are
+    sampled and clamped, mg_task_step advances every env, and observation, action, reward
+    (-error) and done go into a rollout buffer of `horizon` steps, all on the GPU.  The
+    learner's update is not part of it."""
+    from workloads import BLUEROV2_HEAVY, vehicle_variant, initial_state
+    dev = torch.device("cuda:0")
+    E, N = n_envs, 8
+    heavy = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
+    sim = mg.Sim(heavy, E, 0.005, 4)
+    x0 = torch.from_numpy(initial_state(E, sim.state_dim, 9101)).to(dev)
+    sim.reset(state=x0)
+    g = torch.Generator(device="cpu").manual_seed(9102)
+    sim.task_configure({"task": "circle", "lookahead": 4, "radius": 2.0, "omega": 0.5,
+                        "episode_steps": 100},
+                       (torch.randn((3, E), generator=g) * 0.3).to(dev),
+                       (torch.rand(E, generator=g) * 6.283185307179586).to(dev))
+    torch.manual_seed(9103)
+
+    def mlp(n_out):
+        return torch.nn.Sequential(torch.nn.Linear(sim.obs_dim, 256), torch.nn.ELU(),
+                                   torch.nn.Linear(256, 128), torch.nn.ELU(),
+                                   torch.nn.Linear(128, 64), torch.nn.ELU(),
+                                   torch.nn.Linear(64, n_out)).to(dev)
+
+    actor, critic = mlp(N), mlp(1)
+    log_std = torch.full((N,), -1.0, device=dev)
+    buf_obs = torch.empty((horizon, E, sim.obs_dim), device=dev)
+    buf_act = torch.empty((horizon, E, N), device=dev)
+    buf_val = torch.empty((horizon, E), device=dev)
+    buf_rew = torch.empty((horizon, E), device=dev)
+    buf_done = torch.empty((horizon, E), dtype=torch.int32, device=dev)
+    obs = sim.task_observe()
+    err = torch.empty((E,), device=dev)
+    done = torch.empty((E,), dtype=torch.int32, device=dev)
+    nxt = torch.empty_like(obs)
+
+    def one(i):
+        nonlocal obs, nxt
+        h = i % horizon
+        with torch.no_grad():
+            o = obs.t()
+            buf_obs[h].copy_(o)
+            mu = actor(o)
+            a = (mu + torch.randn_like(mu) * log_std.exp()).clamp_(-1.0, 1.0)
+            buf_act[h].copy_(a)
+            buf_val[h].copy_(critic(o).squeeze(1))
+            sim.task_step(a.t().contiguous(), nxt, err, done, reset_state=x0)
+            torch.neg(err, out=buf_rew[h])
+            buf_done[h].copy_(done)
+        obs, nxt = nxt, obs
+
+    for i in range(warmup):
+        one(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one(i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    return {"workload": f"{E} BlueROV2 Heavy envs, circle task (30 observation rows), actor + "
+                        "critic MLP 30-256-128-64 (FP32), Gaussian actions, rollout buffer "
+                        f"of {horizon} steps",
+            "n_envs": E, "steps": steps, "ms_per_step": wall * 1e3 / steps,
+            "env_steps_per_s": E * steps / wall,
+            "sim_seconds_per_wall_second": E * steps * 4 * 0.005 / wall}
+
+
 def summarise_profile(root):
     """Summary of rocprofv3 CSV output under `root` (host-only, no GPU): per-kernel launch
     statistics from kernel_stats.csv; for the k_step launches of a kernel trace the union of
@@ -372,6 +444,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-task", action="store_true")
+    ap.add_argument("--no-policy", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one device copy of 1 GiB (read 1 GiB, write 1 GiB) whose "
@@ -505,6 +578,8 @@ def main():
     del act
     torch.cuda.empty_cache()
 
+    if not args.no_policy:
+        out["policy_in_the_loop"] = [bench_policy(torch, mg, n) for n in (4096, 1 << 16, 1 << 20)]
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, mg)
         out["adjoint_1m_envs"] = bench_adjoint(torch, mg, reps=3, n_envs=1 << 20)

@@ -44,6 +44,11 @@
  * position error of Eq. (4) and the episode bookkeeping (counter, termination,
  * truncation, automatic reset) are written out step by step in FP64; their
  * readings are listed with the design notes.
+ *
+ * The split scheme of Sec. II is also written out: a physics engine steps the
+ * rigid body (M_RB, C_RB, g_RB) by semi-implicit Euler while the hydrodynamic
+ * wrench -M_A a_prev - C_A nu - D nu - g_A, computed from the current state
+ * and the previous sub-step's acceleration a_prev, acts as an external force.
  */
 #include <algorithm>
 #include <cmath>
@@ -400,6 +405,85 @@ void control_step(const Body<T>& b, T* x, const T* a, int S, double dt) {
   T fcmd[kMaxThr];
   thruster_command(b, a, fcmd);
   for (int s = 0; s < S; ++s) rk4_substep(b, x, fcmd, dt);
+}
+
+/* One sub-step of the split scheme (Sec. II): the hydrodynamic wrench of the
+ * current state, with the added-mass term taken from the previous sub-step's
+ * acceleration acc (6), acts on the rigid body as an external force; the
+ * rigid body advances by semi-implicit Euler (velocity first, then position
+ * with the new velocity and the old attitude, attitude with the new angular
+ * rate), q <- q/|q|, the thruster lag by explicit Euler; acc <- the rigid
+ * body's acceleration of this sub-step. */
+template <class T>
+void split_substep(const Body<T>& b, T* x, T* acc, const T* fcmd, double dt) {
+  const T* q = x + 3;
+  const T* nu = x + 7;
+  T* f = x + 13;
+  T R[3][3];
+  rotation(q, R);
+  const T* thrust = b.lag() ? f : fcmd;
+  T tau[6];
+  for (int r = 0; r < 6; ++r) {
+    T s = T(0.0);
+    for (int i = 0; i < b.n_thr; ++i) s += T(b.Balloc[r][i]) * thrust[i];
+    tau[r] = s;
+  }
+  // rigid-body and added-mass matrices apart
+  Body<T> rb = b;
+  for (int i = 0; i < 6; ++i) rb.MA[i] = T(0.0);
+  T MRB[6][6], MAd[6][6], CRB[6][6], CA[6][6];
+  mass_matrix(rb, MRB);
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) MAd[i][j] = (i == j) ? b.MA[i] : T(0.0);
+  coriolis_matrix(MRB, nu, CRB);
+  coriolis_matrix(MAd, nu, CA);
+  // restoring split: g_RB = -[W k ; W r_g x k] (gravity), g_A = [B k ; B r_b x k] (buoyancy)
+  const T W = b.m * T(kG0);
+  T k[3] = {R[2][0], R[2][1], R[2][2]};
+  T gRB[6], gA[6];
+  for (int i = 0; i < 3; ++i) {
+    gRB[i] = -(W * k[i]);
+    gA[i] = b.B * k[i];
+  }
+  T rgk[3], rbk[3];
+  const T rg[3] = {T(b.rg[0]), T(b.rg[1]), T(b.rg[2])};
+  const T rbv[3] = {T(b.rb[0]), T(b.rb[1]), T(b.rb[2])};
+  cross(rg, k, rgk);
+  cross(rbv, k, rbk);
+  for (int i = 0; i < 3; ++i) {
+    gRB[3 + i] = -(W * rgk[i]);
+    gA[3 + i] = b.B * rbk[i];
+  }
+  T rhs6[6];
+  for (int i = 0; i < 6; ++i) {
+    T CRBnu = T(0.0), CAnu = T(0.0);
+    for (int j = 0; j < 6; ++j) {
+      CRBnu += CRB[i][j] * nu[j];
+      CAnu += CA[i][j] * nu[j];
+    }
+    const T Dnu = (b.DL[i] + b.DQ[i] * fabs(nu[i])) * nu[i];
+    const T tau_h = -(b.MA[i] * acc[i]) - CAnu - Dnu - gA[i];
+    rhs6[i] = tau[i] + tau_h - CRBnu - gRB[i];
+  }
+  T a[6];
+  chol_solve6(MRB, rhs6, a);
+  T nun[6];
+  for (int i = 0; i < 6; ++i) nun[i] = nu[i] + T(dt) * a[i];
+  for (int i = 0; i < 3; ++i)
+    x[i] = x[i] + T(dt) * (R[i][0] * nun[0] + R[i][1] * nun[1] + R[i][2] * nun[2]);
+  T om[4] = {T(0.0), nun[3], nun[4], nun[5]};
+  T qd[4];
+  quat_mul(q, om, qd);
+  T qn[4];
+  for (int i = 0; i < 4; ++i) qn[i] = x[3 + i] + T(0.5 * dt) * qd[i];
+  const T n = sqrt(qn[0] * qn[0] + qn[1] * qn[1] + qn[2] * qn[2] + qn[3] * qn[3]);
+  for (int i = 0; i < 4; ++i) x[3 + i] = qn[i] / n;
+  for (int i = 0; i < 6; ++i) {
+    x[7 + i] = nun[i];
+    acc[i] = a[i];
+  }
+  if (b.lag())
+    for (int i = 0; i < b.n_thr; ++i) f[i] = f[i] + T(dt) * (fcmd[i] - f[i]) / T(b.thr_tau);
 }
 
 /* Kinetic energy 1/2 nu^T M nu. */
@@ -909,6 +993,52 @@ int or_task_rollout(const OrVehicle* classes, int n_classes, const int32_t* env_
     if (xT)
       for (int i = 0; i < D; ++i) xT[(size_t)i * E + e] = i < Dc ? x[i] : 0.0;
     if (kT) kT[e] = k;
+  }
+  return 0;
+}
+
+}  // extern "C"
+
+/* ---- split scheme of Sec. II (C entry point) ---------------------------------- */
+extern "C" {
+
+/* T control steps of the split scheme for every env (S sub-steps of dt each,
+ * the throttle frame held), from states x0 [D][E] and previous-sub-step
+ * accelerations acc0 [6][E] (NULL: 0).  traj [T][D][E], xT [D][E] and accT
+ * [6][E] as for or_rollout, each or NULL. */
+int or_split_rollout(const OrVehicle* classes, int n_classes, const int32_t* env_class, int64_t E,
+                     const double* mult, const double* x0, const double* acc0, int D,
+                     const double* act, int nmax, int T, int S, double dt, double* traj,
+                     double* xT, double* accT, int nthreads) {
+  if (E < 0 || T < 0 || S < 1 || n_classes < 1 || D < 13 || D > kMaxState) return -1;
+  for (int c = 0; c < n_classes; ++c) {
+    const OrVehicle& v = classes[c];
+    if (v.n_thr < 1 || v.n_thr > nmax || v.n_thr > kMaxThr) return -1;
+    if (v.thr_tau > 0.0 && 13 + v.n_thr > D) return -1;
+  }
+#pragma omp parallel for schedule(dynamic, 16) num_threads(resolve_threads(nthreads))
+  for (int64_t e = 0; e < E; ++e) {
+    const int cls = env_class ? env_class[e] : 0;
+    double m23[23];
+    if (mult)
+      for (int k = 0; k < 23; ++k) m23[k] = mult[(size_t)k * E + e];
+    Body<double> b = make_body<double>(classes[cls], mult ? m23 : nullptr, nullptr);
+    const int Dc = b.state_dim();
+    double x[kMaxState], acc[6];
+    for (int i = 0; i < Dc; ++i) x[i] = x0[(size_t)i * E + e];
+    for (int i = 0; i < 6; ++i) acc[i] = acc0 ? acc0[(size_t)i * E + e] : 0.0;
+    for (int t = 0; t < T; ++t) {
+      double a[kMaxThr], fcmd[kMaxThr];
+      for (int i = 0; i < b.n_thr; ++i) a[i] = act[((size_t)t * nmax + i) * E + e];
+      thruster_command(b, a, fcmd);
+      for (int s = 0; s < S; ++s) split_substep(b, x, acc, fcmd, dt);
+      if (traj)
+        for (int i = 0; i < D; ++i) traj[((size_t)t * D + i) * E + e] = i < Dc ? x[i] : 0.0;
+    }
+    if (xT)
+      for (int i = 0; i < D; ++i) xT[(size_t)i * E + e] = i < Dc ? x[i] : 0.0;
+    if (accT)
+      for (int i = 0; i < 6; ++i) accT[(size_t)i * E + e] = acc[i];
   }
   return 0;
 }

@@ -120,6 +120,11 @@ def lib():
                                       ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_double, tp, _dp, _dp, _dp, _ip, _dp, _dp, _dp,
                                       _dp, _ip, _dp, _ip, ctypes.c_int]
+        L.or_split_rollout.argtypes = [vp, ctypes.c_int, _ip, ctypes.c_int64, _dp, _dp, _dp,
+                                       ctypes.c_int, _dp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
+                                       ctypes.c_int]
+        L.or_split_rollout.restype = ctypes.c_int
         for name in ("or_alloc", "or_mass_matrix", "or_coriolis_matrix", "or_restoring",
                      "or_rotation", "or_rhs", "or_rollout", "or_track_loss",
                      "or_track_loss_grad", "or_jvp", "or_task_reference", "or_euler_zyx",
@@ -381,3 +386,35 @@ def task_rollout(presets, task, x0, act, n_substeps, dt, center, phase, yaw=None
     if rc != 0:
         raise ValueError("or_task_rollout rejected its arguments")
     return {"obs": obs, "err": err, "done": done, "x": xT, "k": kT}
+
+
+# -- split scheme of Sec. II -----------------------------------------------------------------
+
+def split_rollout(presets, x0, act, n_substeps, dt, env_class=None, mult=None, acc0=None,
+                  want_traj=False, nthreads=0):
+    """The split scheme (rigid body by semi-implicit Euler, hydrodynamic wrench with the
+    added-mass term of the previous sub-step as an external force).  Returns dict with
+    'x' [D][E], 'acc' [6][E] and optionally 'traj' [T][D][E]."""
+    if isinstance(presets, dict):
+        presets = [presets]
+    x0 = _f64(x0)
+    act = _f64(act)
+    D, E = x0.shape
+    T, nmax, E2 = act.shape
+    assert E2 == E
+    vs = (OrVehicle * len(presets))(*[vehicle(p) for p in presets])
+    ec = _i32(env_class)
+    xT = np.zeros((D, E))
+    accT = np.zeros((6, E))
+    traj = np.zeros((T, D, E)) if want_traj else None
+    m, a0 = _f64(mult), _f64(acc0)
+    rc = lib().or_split_rollout(vs, len(presets), ec.ctypes.data_as(_ip) if ec is not None else None,
+                                E, _ptr(m), _ptr(x0), _ptr(a0), D, _ptr(act), nmax, T,
+                                int(n_substeps), float(dt), _ptr(traj), _ptr(xT), _ptr(accT),
+                                int(nthreads))
+    if rc != 0:
+        raise ValueError("or_split_rollout rejected its arguments")
+    out = {"x": xT, "acc": accT}
+    if want_traj:
+        out["traj"] = traj
+    return out

@@ -74,7 +74,7 @@ def test_lagged_added_mass_growth_factor(oracle):
             # 0.5^200 lies below the rounding of the restoring terms that cancel beside it
             assert ratio < 1e-12
     v = _heave_vehicle(5.75)
-    got = oracle.split_rollout(v, _rest(), np.full((3000, 1, 1), 0.6), 1, 0.01)
+    got = oracle.split_rollout(v, _rest(), np.full((20000, 1, 1), 0.6), 1, 0.01)
     assert got["x"][9, 0] == pytest.approx(6.0 / 5.0, rel=1e-9)
 
 

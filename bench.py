@@ -379,6 +379,43 @@ def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16):
             "sim_seconds_per_wall_second": E * steps * 4 * 0.005 / wall}
 
 
+def bench_split(torch, mg, classes, cls, act, x0, mult, n_ctrl=50):
+    """The split scheme of Sec. II (mg_step_split) on the benchmark's envs: its rate, the
+    share of envs that blow up (non-finite or |x| > 1e6) within n_ctrl control steps with
+    the presets (heave and sway added mass above the vehicle mass) and with the added mass
+    scaled by 0.4 (stable), and, for the latter, the position gap to the coupled RK4 step."""
+    import copy
+    E, dev = x0.shape[1], x0.device
+    out = {"workload": f"{E} envs (the benchmark's mix), {n_ctrl} control steps of 16 x 5 ms"}
+    for label, factor in (("presets", 1.0), ("added_mass_x0.4", 0.4)):
+        cl = [copy.deepcopy(v) for v in classes]
+        for v in cl:
+            v["added_mass"] = [a * factor for a in v["added_mass"]]
+        sim = mg.Sim(cl, E, 0.005, 16, env_class=cls)
+        sim.reset(state=x0, param_mult=mult)
+        sim.step_split(act[:2])
+        torch.cuda.synchronize()
+        sim.reset(state=x0, param_mult=mult)
+        t0 = time.perf_counter()
+        sim.step_split(act[:n_ctrl])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        xs = sim.get_state()
+        blown = (~torch.isfinite(xs).all(dim=0)) | (xs.abs().amax(dim=0) > 1e6)
+        res = {"env_steps_per_s": E * n_ctrl * 16 / wall,
+               "blown_share": float(blown.float().mean())}
+        if factor != 1.0:
+            sim.reset(state=x0, param_mult=mult)
+            sim.step(act[:n_ctrl])
+            gap = (xs[:3] - sim.get_state()[:3]).norm(dim=0)
+            res["position_gap_to_rk4_m"] = {"median": float(gap.median()),
+                                            "p99": float(torch.quantile(gap[:1 << 16], 0.99)),
+                                            "max": float(gap.max())}
+        sim.close()
+        out[label] = res
+    return out
+
+
 def summarise_profile(root):
     """Summary of rocprofv3 CSV output under `root` (host-only, no GPU): per-kernel launch
     statistics from kernel_stats.csv; for the k_step launches of a kernel trace the union of
@@ -445,6 +482,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-task", action="store_true")
     ap.add_argument("--no-policy", action="store_true")
+    ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one device copy of 1 GiB (read 1 GiB, write 1 GiB) whose "
@@ -574,6 +612,8 @@ def main():
         }
     if not args.no_task:
         out["task_epilogue"] = bench_task(torch, sim, act, x0)
+    if not args.no_split:
+        out["split_scheme"] = bench_split(torch, mg, classes, cls, act, x0, mult)
     sim.close()
     del act
     torch.cuda.empty_cache()

@@ -175,6 +175,18 @@ mg_status mg_get_params(mg_sim* sim, float* out, int32_t out_on_device);
 /* Waits for the sim's stream; returns MG_ERR_DEVICE if queued work failed. */
 mg_status mg_synchronize(mg_sim* sim);
 
+/* The split integration that Sec. II describes, as a variant of mg_step: a
+ * physics engine advances the rigid body (M_RB, C_RB, g_RB) by semi-implicit
+ * Euler while the hydrodynamic wrench -M_A a_prev - C_A nu - D nu - g_A,
+ * computed from the current state, acts on it as an external force; a_prev
+ * is the env's rigid-body acceleration of its previous sub-step (kept by the
+ * sim, 0 after mg_reset).  Per sub-step: nu += dt a, p += dt R(q) v with the
+ * new v, q += dt/2 q (x) (0, omega) with the new omega then q /= |q|, thruster
+ * lag by explicit Euler.  First order, and unstable on any axis whose added
+ * mass exceeds its rigid-body inertia (the lagged term grows by M_A / M_RB per
+ * sub-step).  Arguments as mg_step (no statistics). */
+mg_status mg_step_split(mg_sim* sim, const float* actions, int32_t n_ctrl, float* traj);
+
 /* ---- Gym-style tasks (Sec. III) ------------------------------------------------------
  * The four control tasks of Sec. III as vectorised environments: station
  * keeping and circle, helix and lemniscate tracking.  A task step is one

@@ -199,6 +199,8 @@ __global__ void __launch_bounds__(256) k_reset(const ResetArgs a) {
   set_env_params(nom, a.param_in ? a.param_in + k : nullptr, a.n, a.param_absolute != 0,
                  a.params, a.derived, a.Ep, j);
   if (a.write_state && a.task_k) a.task_k[j] = 0;
+  if (a.write_state && a.split_acc)
+    for (int i = 0; i < 6; ++i) a.split_acc[i * a.Ep + j] = 0.0f;
 
   if (a.write_state) {
     const int Dc = 13 + (nom.lag ? nom.n_thr : 0);

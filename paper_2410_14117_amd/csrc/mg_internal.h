@@ -95,6 +95,7 @@ struct ResetArgs {
   int32_t param_absolute;      // param_in holds absolute values (else multipliers)
   int32_t write_state;         // 0: keep the state
   int32_t* task_k;             // internal [Ep] episode counters zeroed with the state, or NULL
+  float* split_acc;            // internal [6][Ep] split-scheme accelerations zeroed likewise, or NULL
 };
 
 // Gym-style task of Sec. III (wave-uniform, by value): kind, look-ahead
@@ -124,6 +125,24 @@ struct TaskArgs {
   int32_t* done;               // caller [E] or NULL
   const float* reset_state;    // caller [D][E] or NULL (rest at the origin)
   const float* reset_mult;     // caller [23][E] or NULL (parameters kept)
+};
+
+// The split scheme of Sec. II (rigid body by semi-implicit Euler, the
+// hydrodynamic wrench with the previous sub-step's added-mass acceleration as
+// an external force).
+struct SplitArgs {
+  float* state;                // internal [D][Ep]
+  const float* params;         // internal [23][Ep] absolute
+  const float* derived;        // internal [kNumDerived][Ep]
+  float* acc;                  // internal [6][Ep] previous sub-step's acceleration
+  int64_t Ep, E;
+  const int32_t* perm;
+  int64_t seg_start, seg_len;
+  const float* actions;        // caller [n_ctrl][n_max][E]
+  int32_t n_max, D, n_ctrl, substeps;
+  float* traj;                 // caller [n_ctrl][D][E] or NULL
+  float dt;
+  double zg;                   // this class's CG height below the CO
 };
 
 struct AdjArgs {
@@ -201,6 +220,7 @@ hipError_t launch_stats_finalize(const double* partials, int32_t nblk, int32_t n
                                  double* stats, hipStream_t s);
 hipError_t launch_reset(const ResetArgs& a, hipStream_t s);
 hipError_t launch_task(const ClassConst& cc, const TaskConst& tc, const TaskArgs& a, hipStream_t s);
+hipError_t launch_split(const ClassConst& cc, const SplitArgs& a, hipStream_t s);
 // out[r][perm[j]] = in[r][j] for rows r < rows (internal -> caller order)
 hipError_t launch_gather_out(const float* in, int64_t Ep, float* out, int64_t E, int32_t rows,
                              const int32_t* perm, int64_t n_internal, hipStream_t s);

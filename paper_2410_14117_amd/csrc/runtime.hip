@@ -70,6 +70,8 @@ struct mg_sim {
   TaskConst task{};
   float* task_f = nullptr;     // [5][Ep] centre, curve phase, target yaw
   int32_t* task_k = nullptr;   // [Ep] control steps since each env's episode began
+  // split scheme (mg_step_split): each env's acceleration of its last sub-step
+  float* split_acc = nullptr;  // [6][Ep]
 };
 
 // Class constants the step kernels read from scalar registers.
@@ -297,6 +299,7 @@ mg_status reset_impl(mg_sim* s, const int64_t* ids, int64_t n, const float* stat
   r.param_absolute = absolute;
   r.write_state = write_state;
   r.task_k = s->task_k;
+  r.split_acc = s->split_acc;
   MG_HIP(s, launch_reset(r, s->stream));
   return MG_OK;
 }
@@ -578,7 +581,8 @@ void mg_destroy(mg_sim* s) {
     for (hipEvent_t e : s->ev_fork) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->ev_join) (void)hipEventDestroy(e);
     void* bufs[] = {s->state, s->params, s->derived, s->perm, s->iperm, s->class_of,
-                    s->nominal_dev, s->partials, s->staging, s->segbuf, s->task_f, s->task_k};
+                    s->nominal_dev, s->partials, s->staging, s->segbuf, s->task_f, s->task_k,
+                    s->split_acc};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     (void)hipGetLastError();
@@ -636,6 +640,53 @@ mg_status mg_set_state(mg_sim* s, const float* state) {
 mg_status mg_step(mg_sim* s, const float* actions, int32_t n_ctrl, const float* targets,
                   float* traj, double* stats) {
   return step_common(s, actions, n_ctrl, targets, traj, stats, false);
+}
+
+mg_status mg_step_split(mg_sim* s, const float* actions, int32_t n_ctrl, float* traj) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!actions) return fail(s, MG_ERR_INVALID, "actions is NULL");
+  if (n_ctrl < 1) return fail(s, MG_ERR_INVALID, "n_ctrl must be >= 1");
+  DeviceGuard g(s->device);
+  if (!s->split_acc) {
+    if (hipMalloc(&s->split_acc, (size_t)6 * s->Ep * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(s, MG_ERR_OOM, "split-scheme accelerations");
+    }
+    MG_HIP(s, hipMemsetAsync(s->split_acc, 0, (size_t)6 * s->Ep * sizeof(float), s->stream));
+  }
+  SplitArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.state = s->state;
+  a.params = s->params;
+  a.derived = s->derived;
+  a.acc = s->split_acc;
+  a.Ep = s->Ep;
+  a.E = s->E;
+  a.perm = s->perm;
+  a.actions = actions;
+  a.n_max = s->n_max;
+  a.D = s->D;
+  a.n_ctrl = n_ctrl;
+  a.substeps = s->substeps;
+  a.traj = traj;
+  a.dt = (float)s->dt;
+  hipStream_t st0 = s->stream;
+  for (int k = 1; k < s->n_classes; ++k) {
+    MG_HIP(s, hipEventRecord(s->ev_fork[k - 1], st0));
+    MG_HIP(s, hipStreamWaitEvent(s->aux[k - 1], s->ev_fork[k - 1], 0));
+  }
+  for (int k = 0; k < s->n_classes; ++k) {
+    a.seg_start = s->seg_start[k];
+    a.seg_len = s->seg_len[k];
+    a.zg = s->nominal[k].zg;
+    MG_HIP(s, launch_split(s->cc[k], a, k == 0 ? st0 : s->aux[k - 1]));
+  }
+  for (int k = 1; k < s->n_classes; ++k) {
+    MG_HIP(s, hipEventRecord(s->ev_join[k - 1], s->aux[k - 1]));
+    MG_HIP(s, hipStreamWaitEvent(st0, s->ev_join[k - 1], 0));
+  }
+  return MG_OK;
 }
 
 mg_status mg_task_configure(mg_sim* s, const mg_task* task, const float* center,

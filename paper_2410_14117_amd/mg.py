@@ -133,6 +133,7 @@ _SIGS = {
     "mg_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(MgServerStats)]),
     "mg_server_last_error": (ctypes.c_char_p, [_vp]),
     "mg_server_destroy": (None, [_vp]),
+    "mg_step_split": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp]),
     "mg_task_configure": (ctypes.c_int32, [_vp, ctypes.POINTER(MgTask), _vp, _vp, _vp]),
     "mg_task_obs_dim": (ctypes.c_int32, [_vp]),
     "mg_task_observe": (ctypes.c_int32, [_vp, _vp]),
@@ -299,6 +300,17 @@ class Sim:
         tr = _ptr(traj, torch.float32, (n_ctrl, D, E), "traj")
         stt = _ptr(stats, torch.float64, (n_ctrl, NUM_STATS), "stats")
         return a, tg, tr, stt
+
+    def step_split(self, actions, traj=None):
+        """actions [n_ctrl][N_max][E]: n_ctrl control steps of the split scheme of Sec. II
+        in one launch per class (see mg_step_split)."""
+        import torch
+        n_ctrl = int(actions.shape[0])
+        E, D, N = self.n_envs, self.state_dim, self.action_dim
+        a = _ptr(actions, torch.float32, (n_ctrl, N, E), "actions")
+        tr = _ptr(traj, torch.float32, (n_ctrl, D, E), "traj")
+        self._bind_stream()
+        self._check(lib().mg_step_split(self._h, a, n_ctrl, tr))
 
     # -- Gym-style tasks ---------------------------------------------------------------------
     def task_configure(self, task, center, phase, yaw=None):

@@ -77,6 +77,12 @@ def test_null_sim_calls_are_safe():
     assert L.mg_step(None, None, 1, None, None, None) == mg.MG_ERR_INVALID
     assert L.mg_reset(None, None, 0, None, None) == mg.MG_ERR_INVALID
     assert L.mg_synchronize(None) == mg.MG_ERR_INVALID
+    assert L.mg_step_split(None, None, 1, None) == mg.MG_ERR_INVALID
+    assert L.mg_task_obs_dim(None) == 0
+    assert L.mg_task_configure(None, None, None, None, None) == mg.MG_ERR_INVALID
+    assert L.mg_task_observe(None, None) == mg.MG_ERR_INVALID
+    assert L.mg_task_step(None, None, None, None, None, None, None) == mg.MG_ERR_INVALID
+    assert L.mg_task_counters(None, None) == mg.MG_ERR_INVALID
 
 
 def test_create_without_device_reports_device_error():

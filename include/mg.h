@@ -307,10 +307,11 @@ mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, 
  *   max_queue      bound of the admission queue (0 -> 65536)
  *   reserve_bytes  page memory (>= 0) to create at start (at most the cap),
  *                  with pinned staging for up to 4096 pages joining or
- *                  leaving per tick, so that serving within it allocates
- *                  nothing; 0: pages are created on demand in slabs of 1024
- *                  and staging grows as needed.  Creation fails with
- *                  MG_ERR_OOM if the reservation cannot be had.
+ *                  leaving per tick and 16 pinned result buffers of up to
+ *                  16 MB, so that serving within it allocates nothing; 0:
+ *                  pages are created on demand in slabs of 1024 and staging
+ *                  grows as needed.  Creation fails with MG_ERR_OOM if the
+ *                  reservation cannot be had.
  * mg_request (everything the client passes stays owned by the client and
  * must stay valid until the request completes)
  *   n_envs, n_steps  env count (>= 1) and control steps (>= 1; 1 = a step request)

@@ -717,8 +717,10 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
     for (auto& sl : S->slots)
       ok = ok && sl.init.grow(items) && sl.cols_stage.grow(items * kPageEnvs) &&
            sl.pre.grow(items) && sl.post.grow(items) && sl.gather.grow(items);
+    // result buffers: one per slot in flight plus those the delivery thread
+    // still copies out of (large outputs arriving in bursts), 16 MB each
     const size_t out_floats = std::min<size_t>(items * kPageEnvs * (size_t)S->D, (size_t)1 << 22);
-    for (int i = 0; ok && i < mg_server::kSlots + 2; ++i) {
+    for (int i = 0; ok && i < 16; ++i) {
       S->out_all.push_back(new Mirror<float>());
       S->out_pool.push_back(S->out_all.back());
       ok = S->out_all.back()->grow(out_floats);

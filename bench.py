@@ -56,12 +56,13 @@ def plain_bytes(n_thr, lag):
 
 
 def kernel_source_hash():
+    """Hash of the sources the step kernels are compiled from (their traffic and counters
+    in profiles/ hold only while these are unchanged)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2410_14117_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in ("kernels_step.hip", "fossen_device.h", "mg_internal.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -308,14 +308,15 @@ def bench_task(torch, sim, act, x0, n_steps=60):
             "env_steps_per_s": E * S / (task_ms * 1e-3)}
 
 
-def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16):
+def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16, graph=False):
     """Policy in the loop (the sampling side of the paper's PPO setup, Sec. III): BlueROV2
     Heavy envs on the circle task (m = 4 look-ahead points, 30 observation rows, episodes of
     100 control steps of 4 x 5 ms, automatic reset); per step an actor and a critic MLP
     (30-256-128-64, ELU; FP32, random init) read the observation, Gaussian actions are
     sampled and clamped, mg_task_step advances every env, and observation, action, reward
     (-error) and done go into a rollout buffer of `horizon` steps, all on the GPU.  The
-    learner's update is not part of it."""
+    learner's update is not part of it.  graph=True captures one step (policy, sampling,
+    mg_task_step, buffer writes at a device-side slot index) in a HIP graph and replays it."""
     from workloads import BLUEROV2_HEAVY, vehicle_variant, initial_state
     dev = torch.device("cuda:0")
     E, N = n_envs, 8
@@ -363,18 +364,50 @@ def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16):
             buf_done[h].copy_(done)
         obs, nxt = nxt, obs
 
+    slot = torch.zeros((1,), dtype=torch.int64, device=dev)
+
+    def one_static():
+        # the same step on fixed buffers, the rollout slot kept on the device
+        with torch.no_grad():
+            o = obs.t()
+            buf_obs.index_copy_(0, slot, o.unsqueeze(0))
+            mu = actor(o)
+            a = (mu + torch.randn_like(mu) * log_std.exp()).clamp_(-1.0, 1.0)
+            buf_act.index_copy_(0, slot, a.unsqueeze(0))
+            buf_val.index_copy_(0, slot, critic(o).squeeze(1).unsqueeze(0))
+            sim.task_step(a.t().contiguous(), nxt, err, done, reset_state=x0)
+            buf_rew.index_copy_(0, slot, torch.neg(err).unsqueeze(0))
+            buf_done.index_copy_(0, slot, done.unsqueeze(0))
+            obs.copy_(nxt)
+            slot.add_(1).remainder_(horizon)
+
+    if graph:
+        s_side = torch.cuda.Stream()
+        s_side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s_side):
+            for _ in range(3):
+                one_static()
+        torch.cuda.current_stream().wait_stream(s_side)
+        torch.cuda.synchronize()
+        g_step = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_step):
+            one_static()
+        run = lambda i: g_step.replay()      # noqa: E731
+    else:
+        run = one
     for i in range(warmup):
-        one(i)
+        run(i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        one(i)
+        run(i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sim.close()
     return {"workload": f"{E} BlueROV2 Heavy envs, circle task (30 observation rows), actor + "
                         "critic MLP 30-256-128-64 (FP32), Gaussian actions, rollout buffer "
                         f"of {horizon} steps",
+            "issued": "one HIP graph replay per step" if graph else "eagerly from Python",
             "n_envs": E, "steps": steps, "ms_per_step": wall * 1e3 / steps,
             "env_steps_per_s": E * steps / wall,
             "sim_seconds_per_wall_second": E * steps * 4 * 0.005 / wall}
@@ -621,6 +654,8 @@ def main():
 
     if not args.no_policy:
         out["policy_in_the_loop"] = [bench_policy(torch, mg, n) for n in (4096, 1 << 16, 1 << 20)]
+        out["policy_in_the_loop"] += [bench_policy(torch, mg, n, graph=True)
+                                      for n in (4096, 1 << 16)]
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, mg)
         out["adjoint_1m_envs"] = bench_adjoint(torch, mg, reps=3, n_envs=1 << 20)

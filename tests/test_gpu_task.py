@@ -206,3 +206,42 @@ def test_nonfinite_env_terminates_and_restarts(mgmod):
     sim.close()
     assert d0[5] == 1 and np.sum(d0 != 0) == 1
     assert np.all(d1 == 0) and np.all(np.isfinite(o1))
+
+
+def test_task_step_captured_in_a_graph(mgmod):
+    """mg_task_step captured in a HIP graph (through torch.cuda.graph, with the class
+    launches forked onto the sim's helper streams inside the capture) and replayed three
+    times, with eager work and synchronisations between the replays, matches an eager
+    twin after every replay bitwise."""
+    E = 4096 + 5
+    cls, x0, act, mult, center, phase, yaw, rs, _ = _inputs(E, 4, 91)
+    say("task step graph capture")
+    tk = _task("lemniscate", episode_steps=2)
+    sims = []
+    for _ in range(2):
+        s = mgmod.Sim(CLASSES, E, DT, S, env_class=cls)
+        s.reset(state=dev(x0), param_mult=dev(mult))
+        s.task_configure(tk, dev(center), dev(phase), dev(yaw))
+        sims.append(s)
+    eager, capt = sims
+    a_d, rs_d = dev(act), dev(rs)
+    a_static = a_d[0].clone()
+    bufs = [torch.empty((eager.obs_dim, E), device="cuda"), torch.empty((E,), device="cuda"),
+            torch.empty((E,), dtype=torch.int32, device="cuda")]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        capt.task_step(a_static, *bufs, reset_state=rs_d)
+    torch.cuda.synchronize()
+    for t in range(3):
+        a_static.copy_(a_d[t])
+        g.replay()
+        o, e, d = eager.task_step(a_d[t], reset_state=rs_d)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(bufs[0]), host(o))
+        np.testing.assert_array_equal(host(bufs[1]), host(e))
+        np.testing.assert_array_equal(host(bufs[2]), host(d))
+        np.testing.assert_array_equal(host(capt.get_state()), host(eager.get_state()))
+        _ = torch.ones(1000, device="cuda").sum()     # eager work between replays
+    eager.close()
+    capt.close()

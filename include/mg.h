@@ -164,7 +164,9 @@ mg_status mg_step_plain(mg_sim* sim, const float* actions, int32_t n_ctrl, const
                         float* traj, double* stats);
 /* T control steps as T launches per class (plain != 0: T * substeps
  * launches), replayed from a HIP graph that is captured on first use and
- * cached for this exact argument tuple.  Arguments as mg_step with n_ctrl = T. */
+ * cached for this exact argument tuple (at most 64 tuples per sim; the 65th
+ * empties the cache, after waiting for the sim's stream).  Arguments as
+ * mg_step with n_ctrl = T. */
 mg_status mg_rollout(mg_sim* sim, const float* actions, int32_t T, const float* targets,
                      float* traj, double* stats, int32_t plain);
 /* Copies the state [D][E] to out.  out_on_device != 0: device pointer,

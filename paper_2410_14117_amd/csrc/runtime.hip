@@ -19,6 +19,8 @@ namespace {
 
 thread_local std::string g_create_error;
 
+constexpr size_t kMaxCachedGraphs = 64;   // rollout graphs kept per sim
+
 struct GraphKey {
   int32_t T, plain;
   const void *actions, *targets, *traj, *stats;
@@ -799,6 +801,11 @@ mg_status mg_rollout(mg_sim* s, const float* actions, int32_t T, const float* ta
     hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(s, MG_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    if (s->graphs.size() >= kMaxCachedGraphs) {
+      // bounded cache: a caller cycling through many buffers starts it afresh
+      MG_HIP(s, hipStreamSynchronize(s->stream));
+      clear_graphs(s);
+    }
     it = s->graphs.emplace(key, exec).first;
   }
   MG_HIP(s, hipGraphLaunch(it->second, s->stream));

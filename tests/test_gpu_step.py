@@ -401,3 +401,22 @@ def test_c3_full_size_sampled(mgmod, oracle):
     assert well[in_regular].mean() >= 0.98
     for x in (xf, xp):
         assert _env_err(x[:, sample[well]], clean[:, well]).max() <= TOL_TRAJ
+
+
+def test_rollout_graph_cache_is_bounded(mgmod):
+    """70 rollouts into 70 different trajectory buffers (more than the 64 cached graphs):
+    every replay still writes the same, correct trajectory."""
+    E, T = 64, 2
+    x0 = initial_state(E, 13, 91)
+    act = dev(actions(T, 6, E, 92))
+    sim = mgmod.Sim(BLUEROV2, E, 0.01, 1)
+    say("rollout graph cache bound")
+    big = torch.zeros((70, T, 13, E), dtype=torch.float32, device="cuda")
+    for i in range(70):
+        sim.reset(state=dev(x0))
+        sim.rollout(act, traj=big[i])
+    torch.cuda.synchronize()
+    ref = host(big[0])
+    for i in range(1, 70):
+        np.testing.assert_array_equal(host(big[i]), ref)
+    sim.close()

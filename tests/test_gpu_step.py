@@ -420,3 +420,48 @@ def test_rollout_graph_cache_is_bounded(mgmod):
     for i in range(1, 70):
         np.testing.assert_array_equal(host(big[i]), ref)
     sim.close()
+
+
+@pytest.mark.parametrize("n_thr", [1, 3])
+def test_few_thruster_classes(mgmod, oracle, n_thr):
+    """Vehicles with 1 and 3 lagged thrusters (the smallest template instantiations),
+    quadratic map, mixed with a BlueROV2 class: one control step and 30 steps vs the
+    oracle."""
+    E = 700
+    small = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
+    small = dict(small)
+    small["thr_pos"] = small["thr_pos"][:n_thr]
+    small["thr_dir"] = small["thr_dir"][:n_thr]
+    classes = [LAGGED["bluerov2"], small]
+    cls = env_classes(E, "bernoulli", 71)
+    x0 = initial_state(E, 19, 72)
+    x0[13 + n_thr:, cls == 1] = 0
+    act = actions(30, 6, E, 73)
+    mult = param_multipliers(E, 0.2, 74)
+    say("few thrusters", n_thr)
+    tr, _, _ = _run(mgmod, classes, x0, act, 0.005, 4, env_class=cls, mult=mult)
+    ref = oracle.rollout(classes, x0, act, 4, 0.005, env_class=cls, mult=mult, want_traj=True)
+    assert rel_err(tr[0], ref["traj"][0]) <= TOL_ONE_STEP
+    assert rel_err(tr, ref["traj"]) <= 1e-4
+
+
+def test_invalid_calls_raise_and_leave_the_sim_usable(mgmod):
+    """Zero control steps, a task step before a task is configured and a split step of zero
+    control steps are rejected (MG_ERR_INVALID) without touching the state."""
+    E = 64
+    sim = mgmod.Sim(BLUEROV2, E, 0.01, 1)
+    x0 = initial_state(E, 13, 81)
+    sim.reset(state=dev(x0))
+    act = dev(actions(1, 6, E, 82))
+    say("invalid calls")
+    with pytest.raises(mgmod.MgError):
+        sim.step(act[:0])
+    with pytest.raises(mgmod.MgError):
+        sim.step_split(act[:0])
+    with pytest.raises(mgmod.MgError):
+        sim.obs_dim = 12
+        sim.task_step(act[0])
+    np.testing.assert_array_equal(host(sim.get_state()), x0)
+    sim.step(act)
+    assert np.isfinite(host(sim.get_state())).all()
+    sim.close()

@@ -12,6 +12,21 @@
 
 namespace mg {
 
+// The forward is held to three resident waves per SIMD (168 VGPRs; the few
+// values it then spills lie outside the control-step loop).  The backward
+// kernel needs about 320 registers (VGPRs + AGPRs), one wave per SIMD; its
+// WAVES = 2 instantiation is squeezed into 256 and spills about 50 values
+// inside the sub-step VJP to scratch.  That pays only when the launch has more
+// waves than one per SIMD across the chip (launch_adj_t picks it then).
+#ifndef MG_ADJ_FWD_WAVES_PER_EU
+#define MG_ADJ_FWD_WAVES_PER_EU 3
+#endif
+#if MG_ADJ_FWD_WAVES_PER_EU > 0
+#define MG_ADJ_FWD_ATTR __attribute__((amdgpu_waves_per_eu(MG_ADJ_FWD_WAVES_PER_EU)))
+#else
+#define MG_ADJ_FWD_ATTR
+#endif
+
 template <int N>
 __device__ __forceinline__ void load_command(const ClassConst& cc, const AdjArgs& a, int t,
                                              int64_t c, float (&act)[N], float (&fcmd)[N],
@@ -24,7 +39,7 @@ __device__ __forceinline__ void load_command(const ClassConst& cc, const AdjArgs
 }
 
 template <int N, bool LAG>
-__global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const ClassConst cc) {
+__global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_fwd(const AdjArgs a, const ClassConst cc) {
   constexpr int D = Dims<N, LAG>::D;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;
@@ -57,8 +72,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_fwd(const AdjArgs a, const Class
   for (int i = 0; i < D; ++i) a.state[i * a.Ep + j] = x[i];
 }
 
-template <int N, bool LAG>
-__global__ void __launch_bounds__(kBlock) k_adj_bwd(const AdjArgs a, const ClassConst cc) {
+template <int N, bool LAG, int WAVES>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAVES)))
+k_adj_bwd(const AdjArgs a, const ClassConst cc) {
   constexpr int D = Dims<N, LAG>::D;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;
@@ -153,8 +169,12 @@ static hipError_t launch_adj_t(bool backward, const ClassConst& cc, const AdjArg
                                hipStream_t s) {
   const int64_t nblk = (a.seg_len + kBlock - 1) / kBlock;
   if (nblk == 0) return hipSuccess;
-  if (backward)
-    hipLaunchKernelGGL((k_adj_bwd<N, LAG>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a, cc);
+  // one wave per SIMD over the whole device: n_cu CUs x 4 SIMDs x 64 lanes
+  const bool crowded = a.seg_len > (int64_t)a.n_cu * 4 * 64;
+  if (backward && crowded)
+    hipLaunchKernelGGL((k_adj_bwd<N, LAG, 2>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a, cc);
+  else if (backward)
+    hipLaunchKernelGGL((k_adj_bwd<N, LAG, 1>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a, cc);
   else
     hipLaunchKernelGGL((k_adj_fwd<N, LAG>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a, cc);
   return hipGetLastError();

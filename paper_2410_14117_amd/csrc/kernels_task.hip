@@ -110,9 +110,12 @@ __device__ __forceinline__ void curve_sincos(const TaskConst& tc, double t, doub
 
 }  // namespace
 
+// Held to three resident waves per SIMD (at most 168 VGPRs), the step kernel's
+// occupancy: left to itself the compiler gives the 8-thruster lag variant 170
+// registers for the epilogue, which leaves room for two waves only.
 template <int N, bool LAG>
-__global__ void __launch_bounds__(kBlock) k_task(const TaskArgs a, const ClassConst cc,
-                                                 const TaskConst tc) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+k_task(const TaskArgs a, const ClassConst cc, const TaskConst tc) {
   constexpr int D = Dims<N, LAG>::D;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;

@@ -162,6 +162,7 @@ struct AdjArgs {
   float* gx0;                  // caller [D][E] or NULL
   float* segbuf;               // internal [K * S][Dc][Ep] scratch (Dc = class state width)
   float zb;                    // class z_b (for dL/dB through h_z)
+  int32_t n_cu;                // compute units (picks the backward kernel's occupancy)
 };
 
 // ---- serving loop (kernels_serve.hip) -------------------------------------

@@ -34,6 +34,7 @@ struct GraphKey {
 
 struct mg_sim {
   int device = 0;
+  int n_cu = 0;                      // compute units of the device
   hipStream_t stream = nullptr;      // caller's stream (not owned)
   hipStream_t cap_stream = nullptr;  // owned, used only to capture graphs
   // one helper stream per class after the first: the classes' launches are
@@ -358,6 +359,7 @@ AdjArgs adj_args(mg_sim* s, const float* actions, int32_t T, int32_t K) {
   a.substeps = s->substeps;
   a.ckpt_every = K;
   a.dt = (float)s->dt;
+  a.n_cu = s->n_cu;
   return a;
 }
 
@@ -471,8 +473,16 @@ mg_status mg_create(const mg_config* cfg, mg_sim** out) {
   }
   if (cfg->device < 0 || cfg->device >= ndev) return fail(nullptr, MG_ERR_INVALID, "bad device ordinal");
 
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, cfg->device) != hipSuccess ||
+      n_cu < 1) {
+    (void)hipGetLastError();
+    return fail(nullptr, MG_ERR_DEVICE, "cannot query the device's compute units");
+  }
+
   mg_sim* s = new mg_sim();
   s->device = cfg->device;
+  s->n_cu = n_cu;
   s->stream = (hipStream_t)cfg->stream;
   s->E = E;
   s->n_classes = cfg->n_classes;

@@ -198,3 +198,36 @@ def test_mixed_classes_interleaved(mgmod, oracle):
             assert np.all(g_act[:, N:, e] == 0)
             assert _rel(g_th[:, e], r_th[:, kk]) <= TOL_GRAD
             assert _rel(g_x0[:D, e], r_x0[:, kk]) <= TOL_GRAD
+
+
+def test_crowded_backward_variant(mgmod, oracle):
+    """A class segment with more envs than one wave per SIMD across the device takes the
+    backward kernel built for two waves per SIMD (registers squeezed, some spilled): its
+    gradients equal, bitwise, those of the one-wave kernel on a small launch of the same envs,
+    and match the oracle on a sample that includes the ragged tail."""
+    v = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    E, T, K, S, dt = n_cu * 4 * 64 + 3 * 64 + 37, 6, 3, 2, 0.005
+    x0 = initial_state(E, 21, 341)
+    x0[13:] = np.random.default_rng(342).uniform(-20, 20, size=(8, E)).astype(np.float32)
+    act = actions(T, 8, E, 343)
+    mult = param_multipliers(E, 0.2, 344)
+    pref, qref = circle_waypoints(T, E, 0.02, 345)
+    say(f"crowded adjoint E={E}")
+    _, g_act, g_th, g_x0, _ = _gpu_grads(mgmod, v, x0, act, mult, pref, qref, S, dt, K)
+    small = np.r_[0:2048, E - 2048:E]
+    say(f"one-wave adjoint E={small.size}")
+    _, s_act, s_th, s_x0, _ = _gpu_grads(mgmod, v, x0[:, small], act[:, :, small],
+                                         mult[:, small], pref[:, :, small], qref[:, :, small],
+                                         S, dt, K)
+    np.testing.assert_array_equal(g_act[:, :, small], s_act)
+    np.testing.assert_array_equal(g_th[:, small], s_th)
+    np.testing.assert_array_equal(g_x0[:, small], s_x0)
+    sub = np.r_[0, 1, E // 3, E // 2, E - 40, E - 2, E - 1]
+    _, r_act, r_th, r_x0 = oracle.track_loss_grad(
+        v, x0[:, sub], act[:, :, sub], S, dt, pref[:, :, sub], qref[:, :, sub],
+        mult=mult[:, sub], want_x0=True)
+    for k, e in enumerate(sub):
+        assert _rel(g_act[:, :, e], r_act[:, :, k]) <= TOL_GRAD
+        assert _rel(g_th[:, e], r_th[:, k]) <= TOL_GRAD
+        assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD

@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "env-steps/s of batched Fossen RK4 step at 1M envs; served p50/p99 latency"
 PEAK_FP32_VALU = 157.3e12      # MI355X published FP32 vector peak (packed)
+# one FP32 FMA per lane per clock without packed math or dual issue:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+PEAK_FP32_SINGLE_ISSUE = 78.6e12
 PEAK_HBM = 8.0e12
 
 
@@ -46,6 +49,20 @@ def substep_flops(n_thr, lag, substeps):
     lag_part = 48 if lag else 0
     per_ctrl = (29 * n_thr + 2) if lag else (14 * n_thr + 8)
     return core + lag_part + per_ctrl / substeps
+
+
+def split_substep_flops(n_thr, lag, substeps):
+    """Flops of one env-substep of the split scheme as its kernel formulates it (FMA = 2):
+    the momentum M nu (14), the residual tau - C nu - D nu - g without the kinematic rows
+    (83: the shared right-hand-side code's 130 less the 47 of the kinematic rows, which
+    the split update does not use and the compiler drops), the lagged added-mass term
+    (12), M_RB^-1 applied to the residual (14), the velocity, position and quaternion
+    updates (12 + 36 + 28), the renormalisation (12) and, with a thruster lag, the lag
+    wrench B (f - f_cmd) added to the command wrench and the lag-state update (16 N);
+    plus, per control step, the throttle map and the command wrench (14 N - 6) spread
+    over the sub-steps."""
+    core = 14 + 83 + 12 + 14 + 12 + 36 + 28 + 12
+    return core + (16 * n_thr if lag else 0) + (14 * n_thr - 6) / substeps
 
 
 def plain_bytes(n_thr, lag):
@@ -79,8 +96,9 @@ def load_traffic(kernel_key):
     return d.get(kernel_key)
 
 
-def cpu_baseline(n_envs=8192, n_ctrl=200):
-    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+def cpu_baseline(n_envs=1 << 16, n_ctrl=200, n_envs_1t=1024):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload (2^16 envs on
+    all host threads, about 10 s on 16 threads; and 1024 envs on one thread)."""
     from oracle import oracle
     from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
                            actions, param_multipliers, env_classes)
@@ -97,10 +115,22 @@ def cpu_baseline(n_envs=8192, n_ctrl=200):
     oracle.rollout(classes, x0, act, c.substeps, c.dt_sub, env_class=cls, mult=mult,
                    want_stats=True, nthreads=threads)
     dt = time.perf_counter() - t0
+    # one thread, on the first 512 envs of each class
+    sel = np.r_[0:n_envs_1t // 2, n_envs // 2:n_envs // 2 + n_envs_1t // 2]
+    t0 = time.perf_counter()
+    oracle.rollout(classes, np.ascontiguousarray(x0[:, sel]),
+                   np.ascontiguousarray(act[:, :, sel]), c.substeps, c.dt_sub,
+                   env_class=cls[sel], mult=np.ascontiguousarray(mult[:, sel]), want_stats=True,
+                   nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n_envs * n_ctrl * c.substeps / dt, "unit": "env-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n_envs} envs (half BlueROV2, half Heavy) x {n_ctrl} control steps x "
-                      f"{c.substeps} RK4 sub-steps, FP64, with statistics; {dt:.2f} s"}
+                      f"{c.substeps} RK4 sub-steps, FP64, with statistics; {dt:.2f} s on "
+                      f"{threads} threads",
+            "value_1_thread": n_envs_1t * n_ctrl * c.substeps / dt1,
+            "sample_1_thread": f"{n_envs_1t} of those envs (half of each class), same steps, "
+                               f"one thread; {dt1:.2f} s"}
 
 
 def bench_adjoint(torch, mg, reps=5, n_envs=None):
@@ -266,7 +296,7 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
             "submit_lag_p99_ms": float(np.percentile(lags, 99) / 1e6)}
 
 
-def bench_task(torch, sim, act, x0, n_steps=60):
+def bench_task(torch, sim, act, x0, n_b, n_h, n_steps=60):
     """Gym-style circle tracking on the benchmark's envs: 4 look-ahead points in the
     observation (30 rows), episodes of 100 control steps with automatic reset, the error of
     Eq. (4) and the done flags; n_steps task steps (one launch per class each, issued from
@@ -311,13 +341,22 @@ def bench_task(torch, sim, act, x0, n_steps=60):
         task_ms = min(task_ms, timed(task_fn))
         step_ms = min(step_ms, timed(step_fn))
     S = sim.substeps
+    flops = S * (n_b * substep_flops(6, True, S) + n_h * substep_flops(8, True, S))
     return {"workload": f"{E} envs (the benchmark's mix), circle tracking, m = 4 look-ahead "
                         "points, episodes of 100 control steps, automatic reset",
             "obs_rows": sim.obs_dim, "ms_per_task_step": task_ms,
             "ms_per_plain_control_step_call": step_ms,
             "epilogue_overhead": task_ms / step_ms - 1.0,
             "env_task_steps_per_s": E / (task_ms * 1e-3),
-            "env_steps_per_s": E * S / (task_ms * 1e-3)}
+            "env_steps_per_s": E * S / (task_ms * 1e-3),
+            "roofline": {"bound": "alu", "kernel": "k_task<6|8,lag>: the fused control step and "
+                                                   "the task epilogue, both class launches",
+                         "achieved": flops / (task_ms * 1e-3) / 1e12,
+                         "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": flops / (task_ms * 1e-3) / PEAK_FP32_VALU,
+                         "counted": "the control step's flops (the fused step's tally); the "
+                                    "epilogue's sincos, atan2 and FP64 work is not counted",
+                         "epilogue_bytes_per_env": 4 * sim.obs_dim + 8 + 24}}
 
 
 def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16, graph=False):
@@ -432,7 +471,13 @@ def bench_split(torch, mg, classes, cls, act, x0, mult, n_ctrl=50):
     scaled by 0.4 (stable), and, for the latter, the position gap to the coupled RK4 step."""
     import copy
     E, dev = x0.shape[1], x0.device
-    out = {"workload": f"{E} envs (the benchmark's mix), {n_ctrl} control steps of 16 x 5 ms"}
+    n_ctrl = min(n_ctrl, act.shape[0])
+    n_b = int((cls == 0).sum())
+    n_h = E - n_b
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"workload": f"{E} envs (the benchmark's mix), {n_ctrl} control steps of 16 x 5 ms "
+                       "in one launch per class"}
     for label, factor in (("presets", 1.0), ("added_mass_x0.4", 0.4)):
         cl = [copy.deepcopy(v) for v in classes]
         for v in cl:
@@ -442,14 +487,25 @@ def bench_split(torch, mg, classes, cls, act, x0, mult, n_ctrl=50):
         sim.step_split(act[:2])
         torch.cuda.synchronize()
         sim.reset(state=x0, param_mult=mult)
-        t0 = time.perf_counter()
-        sim.step_split(act[:n_ctrl])
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        e0.record(stream)
+        sim.step_split(act[:n_ctrl])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
         xs = sim.get_state()
         blown = (~torch.isfinite(xs).all(dim=0)) | (xs.abs().amax(dim=0) > 1e6)
-        res = {"env_steps_per_s": E * n_ctrl * 16 / wall,
-               "blown_share": float(blown.float().mean())}
+        flops = n_ctrl * 16 * (n_b * split_substep_flops(6, True, 16) +
+                               n_h * split_substep_flops(8, True, 16))
+        res = {"env_steps_per_s": E * n_ctrl * 16 / (ms * 1e-3),
+               "blown_share": float(blown.float().mean()),
+               "roofline": {"bound": "alu", "kernel": "k_split<6|8,lag>, both class launches",
+                            "achieved": flops / (ms * 1e-3) / 1e12,
+                            "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                            "frac": flops / (ms * 1e-3) / PEAK_FP32_VALU,
+                            "flops_per_env_substep": {
+                                "bluerov2": split_substep_flops(6, True, 16),
+                                "heavy": split_substep_flops(8, True, 16)}}}
         if factor != 1.0:
             sim.reset(state=x0, param_mult=mult)
             sim.step(act[:n_ctrl])
@@ -626,6 +682,8 @@ def main():
         "sim_seconds_per_wall_second": value * c.dt_sub,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "peak_single_issue": PEAK_FP32_SINGLE_ISSUE / 1e12,
+                     "frac_single_issue": achieved / PEAK_FP32_SINGLE_ISSUE,
                      "traffic": load_traffic("k_step_fused_control_step"),
                      "kernel": "k_step<6|8,lag> fused: the BlueROV2 and Heavy launches of one "
                                "control step (16 RK4 sub-steps each), run concurrently",
@@ -657,7 +715,7 @@ def main():
             "speedup_fused_vs_plain": plain_ms / fused_ms,
         }
     if not args.no_task:
-        out["task_epilogue"] = bench_task(torch, sim, act, x0)
+        out["task_epilogue"] = bench_task(torch, sim, act, x0, n_b, n_h)
     if not args.no_split:
         out["split_scheme"] = bench_split(torch, mg, classes, cls, act, x0, mult)
     sim.close()

@@ -465,3 +465,50 @@ def test_invalid_calls_raise_and_leave_the_sim_usable(mgmod):
     sim.step(act)
     assert np.isfinite(host(sim.get_state())).all()
     sim.close()
+
+
+@pytest.mark.slow
+def test_largest_env_count_offsets_beyond_32_bits(mgmod, oracle):
+    """2^28 + 37 mixed envs with Bernoulli classes (the class permutation spans the whole
+    range): state offsets reach 5.6e9 elements (22.5 GB), past any 32-bit index.  One
+    control step of 2 sub-steps from device-generated inputs; every env stays finite, and
+    128 envs spread over the range and at its end match the oracle within the one-step
+    tolerance."""
+    free = torch.cuda.mem_get_info()[0]
+    if free < (230 << 30):
+        pytest.skip(f"needs ~230 GB of free device memory, {free >> 30} GB free")
+    E, S, dt = (1 << 28) + 37, 2, 0.005
+    classes = [LAGGED["bluerov2"], LAGGED["heavy"]]
+    cls = (np.random.default_rng(71).random(E) < 0.5).astype(np.int32)
+    say(f"largest env count E={E}")
+    g = torch.Generator(device="cuda").manual_seed(72)
+    x0 = torch.empty((21, E), dtype=torch.float32, device="cuda")
+    x0[0:3].uniform_(-1.0, 1.0, generator=g)
+    x0[3:7].normal_(generator=g)
+    x0[3:7] /= x0[3:7].norm(dim=0, keepdim=True)
+    x0[7:13].uniform_(-0.5, 0.5, generator=g)
+    x0[13:].uniform_(-20.0, 20.0, generator=g)
+    act = torch.empty((1, 8, E), dtype=torch.float32, device="cuda").uniform_(-1.2, 1.2,
+                                                                             generator=g)
+    mult = torch.empty((23, E), dtype=torch.float32, device="cuda").uniform_(0.8, 1.2,
+                                                                            generator=g)
+    sim = mgmod.Sim(classes, E, dt, S, env_class=cls)
+    sim.reset(state=x0, param_mult=mult)
+    sim.step(act)
+    out = sim.get_state()
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
+    rng = np.random.default_rng(73)
+    idx = np.unique(np.r_[0:32, E // 2 - 16:E // 2 + 16, E - 32:E,
+                          rng.integers(0, E, 32)])
+    it = torch.from_numpy(idx).to("cuda")
+    xs, acts, ms = host(x0[:, it]), host(act[:, :, it]), host(mult[:, it])
+    got = host(out[:, it])
+    del out, x0, act, mult
+    sim.close()
+    torch.cuda.empty_cache()
+    c = cls[idx]
+    xs[19:, c == 0] = 0.0
+    got[19:, c == 0] = 0.0
+    ref = oracle.rollout(classes, xs, acts, S, dt, env_class=c, mult=ms)
+    assert rel_err(got, ref["x"]) <= TOL_ONE_STEP

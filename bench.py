@@ -185,7 +185,7 @@ def bench_adjoint(torch, mg, reps=5, n_envs=None):
 
 
 def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup_s=0.5,
-                  reserve_bytes=2 << 30):
+                  reserve_bytes=2 << 30, steps_per_tick=1):
     """C5: 32 clients with Poisson arrivals (2000 req/s aggregate), env counts log-uniform in
     [16, 65536], half step requests (1 control step) and half rollouts (1..64 steps), mixed
     BlueROV2 / Heavy (+-20 % randomisation, 4 RK4 sub-steps of 5 ms per control step),
@@ -209,7 +209,7 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
     act_d = torch.from_numpy(actions(LMAX, 8, P, c.seed_base + 3)).to(dev)
     torch.cuda.synchronize()
     srv = mg.Server(classes, c.dt_sub, c.substeps, fifo_plain=fifo_plain,
-                    reserve_bytes=reserve_bytes)
+                    reserve_bytes=reserve_bytes, steps_per_tick=steps_per_tick)
     n_clients, rate = c.extra["clients"], c.extra["rate"]
 
     def make_trace(seconds, trace_seed):
@@ -233,12 +233,18 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
 
     def run(trace):
         # one thread submits at the scheduled times (open loop: latency counts from the
-        # scheduled arrival); then every request is waited for
+        # scheduled arrival); then every request is waited for.  The clients' result
+        # buffers are allocated and touched before the trace starts, as a serving client
+        # keeps them (fresh memory would add its page faults to the measured latency).
         results, lags = [], []
+        sizes = [D * n for _, _, n, _, _ in trace]
+        arena = np.ones(sum(sizes), np.float32)
+        starts = np.concatenate([[0], np.cumsum(sizes)])
+        outs = [arena[starts[i]:starts[i + 1]].reshape(D, -1) for i in range(len(trace))]
         t0 = mg.Server.clock_ns() + 50_000_000
 
         def submitter():
-            for _, t, n, L, off in trace:
+            for i, (_, t, n, L, off) in enumerate(trace):
                 at = t0 + int(t * 1e9)
                 while True:
                     wait_ns = at - mg.Server.clock_ns()
@@ -247,9 +253,8 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
                     if wait_ns > 300_000:
                         time.sleep((wait_ns - 200_000) * 1e-9)
                 lags.append(mg.Server.clock_ns() - at)
-                out = np.empty((D, n), np.float32)
                 st, tk = srv.submit(n, L, x0_d.data_ptr() + 4 * off, act_d.data_ptr() + 4 * off,
-                                    P, out, env_class=cls[off:off + n],
+                                    P, outs[i], env_class=cls[off:off + n],
                                     mult_ptr=mult_d.data_ptr() + 4 * off, arrival_ns=at)
                 results.append((st, tk, n, L))
 
@@ -279,6 +284,7 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
             "requests": len(trace), "completed": int(len(lats)),
             "offered_req_per_s": len(trace) / duration_s, "trace_s": duration_s,
             "warmup_trace_s": warmup_s, "reserved_bytes": reserve_bytes,
+            "steps_per_tick": steps_per_tick,
             "wall_s": wall, "req_per_s": len(lats) / wall,
             "env_control_steps_per_s": env_steps / wall,
             "env_steps_per_s": env_steps * c.substeps / wall,
@@ -730,9 +736,11 @@ def main():
         out["adjoint"] = bench_adjoint(torch, mg)
         out["adjoint_1m_envs"] = bench_adjoint(torch, mg, reps=3, n_envs=1 << 20)
     if not args.no_serve:
-        cb = bench_serving(torch, mg, args.serve_seconds)
+        cb = bench_serving(torch, mg, args.serve_seconds, steps_per_tick=8)
+        cb1 = bench_serving(torch, mg, args.serve_seconds, steps_per_tick=1)
         base = bench_serving(torch, mg, args.serve_seconds, fifo_plain=True)
-        out["serving"] = {"continuous_batching": cb, "baseline_fifo_plain": base,
+        out["serving"] = {"continuous_batching": cb, "continuous_batching_1_step_per_tick": cb1,
+                          "baseline_fifo_plain": base,
                           "p99_speedup_vs_baseline": base["p99_ms"] / cb["p99_ms"]}
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define MG_ABI_VERSION 2u
+#define MG_ABI_VERSION 3u
 #define MG_MAX_THRUSTERS 8
 #define MG_MAX_CLASSES 16
 #define MG_NUM_PARAMS 23  /* m, Ixx, Iyy, Izz, M_A(6), D_L(6), D_Q(6), B */
@@ -314,6 +314,14 @@ mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, 
  *                  pages are created on demand in slabs of 1024 and staging
  *                  grows as needed.  Creation fails with MG_ERR_OOM if the
  *                  reservation cannot be had.
+ *   steps_per_tick most control steps (0 -> 1, at most 64) a page advances per
+ *                  tick: each active request advances min(steps_per_tick,
+ *                  steps it has left), its states held in registers across
+ *                  them.  More steps per tick cut the host's per-tick cost for
+ *                  long rollouts (a 64-step request needs 64 / steps_per_tick
+ *                  ticks); a request that arrives joins at the next tick, which
+ *                  then lasts as long as its longest page's steps.  Results do
+ *                  not depend on it.  Must be 0 or 1 with fifo_plain.
  * mg_request (everything the client passes stays owned by the client and
  * must stay valid until the request completes)
  *   n_envs, n_steps  env count (>= 1) and control steps (>= 1; 1 = a step request)
@@ -340,6 +348,8 @@ typedef struct {
   int32_t fifo_plain;
   int32_t max_queue;
   int64_t reserve_bytes;
+  int32_t steps_per_tick;
+  int32_t reserved;
 } mg_server_config;
 
 typedef struct {

@@ -1,17 +1,20 @@
 // kernels_serve.hip -- device side of the continuous-batching serving loop:
-// page initialisation (state + per-env factorisation), the persistent tick
-// that advances every active page by one control step, and the gather of a
-// finished request's states into caller order.
+// the join of admitted pages (state + per-env factorisation, tick-list entry),
+// the tick that advances the active pages of every class by up to `steps`
+// control steps (as many as each request has left), and the leave of finished
+// pages (states into the tick's result staging, list entry emptied).
 #include "fossen_device.h"
 
 namespace mg {
 
 // one block of 64 threads per admitted page
-__global__ void __launch_bounds__(64) k_serve_init(const ServeInitItem* __restrict__ items,
+__global__ void __launch_bounds__(64) k_serve_join(const ServeInitItem* __restrict__ items,
+                                                   ServeTickItem* __restrict__ list,
                                                    const ClassNominal* __restrict__ nominal,
                                                    int32_t Dmax) {
   const ServeInitItem it = items[blockIdx.x];
   const int lane = threadIdx.x;
+  if (lane == 0) list[it.list_index] = it.item;
   const int32_t col32 = it.cols_src[lane];
   it.cols[lane] = col32;
   const int64_t col = col32;
@@ -33,30 +36,27 @@ __global__ void __launch_bounds__(64) k_serve_init(const ServeInitItem* __restri
     it.block[i * kPageEnvs + lane] = i < Dc ? it.x0[i * it.ld + col] : 0.0f;
 }
 
+// One page (64 envs, one per lane) of class constants cc: the request's
+// control steps [first, first + cnt) with the state in registers throughout.
 template <int N, bool LAG>
-__global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickItem* __restrict__ items,
-                                                       const ServeTickHeader* __restrict__ hdr,
-                                                       int32_t cls, const ClassConst cc,
-                                                       int32_t Dmax, int32_t n_max,
-                                                       int32_t substeps, float dt) {
+__device__ __forceinline__ void serve_page(const ServeTickItem& it, const ClassConst& cc,
+                                           const ServeTickArgs& a, int lane) {
   constexpr int D = Dims<N, LAG>::D;
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  const int n = hdr->count[cls];
-  const int64_t tick = hdr->tick;
-  const StepConstT<float> sc = make_step_const(cc, dt);
-  for (int e = wave; e < n; e += nwaves) {
-    const ServeTickItem it = items[e];
-    if (!it.block) continue;
-    const int64_t col = it.cols[lane];
-    if (col < 0) continue;
-    float x[D];
+  const int64_t col = it.cols[lane];
+  if (col < 0) return;
+  const StepConstT<float> sc = make_step_const(cc, a.dt);
+  float x[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) x[i] = it.block[i * kPageEnvs + lane];
-    const EnvConst P = load_env_const(it.block + Dmax * kPageEnvs, kPageEnvs, lane);
-    const HalfInvT<float> A = half_step_inverse(P, sc.h2);
-    const float* af = it.actions + (tick - it.t0) * n_max * it.ld + col;
+  for (int i = 0; i < D; ++i) x[i] = it.block[i * kPageEnvs + lane];
+  const EnvConst P = load_env_const(it.block + a.Dmax * kPageEnvs, kPageEnvs, lane);
+  const HalfInvT<float> A = half_step_inverse(P, sc.h2);
+  // the host keeps a page in the list only while first < L, so the action rows
+  // read stay below L
+  const int64_t first = a.tick - it.t0;
+  const int64_t left = (int64_t)it.L - first;
+  const int64_t cnt = a.steps < left ? (int64_t)a.steps : left;
+  for (int64_t k = 0; k < cnt; ++k) {
+    const float* af = it.actions + (first + k) * a.n_max * it.ld + col;
     float act[N], fcmd[N], gcmd[6];
 #pragma unroll
     for (int i = 0; i < N; ++i) act[i] = af[i * it.ld];
@@ -64,70 +64,86 @@ __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickItem* __re
     command_wrench<N>(cc, fcmd, gcmd);
     // substeps is the server's S (cc.rho_s = rho^S) or, for the FIFO plain
     // baseline, 1 (rho)
-    control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, substeps, substeps == 1 ? cc.rho : cc.rho_s);
+    control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, a.substeps,
+                         a.substeps == 1 ? cc.rho : cc.rho_s);
+  }
 #pragma unroll
-    for (int i = 0; i < D; ++i) it.block[i * kPageEnvs + lane] = x[i];
+  for (int i = 0; i < D; ++i) it.block[i * kPageEnvs + lane] = x[i];
+}
+
+// One wave per list entry over the entries of all classes (class c's entries
+// follow those of classes 0..c-1); the wave's class picks the instantiation,
+// so the classes' pages run side by side in one launch.
+__global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  int total = 0;
+  for (int c = 0; c < a.n_classes; ++c) total += a.count[c];
+  for (int e = wave; e < total; e += nwaves) {
+    int c = 0, idx = e;
+    while (idx >= a.count[c]) {
+      idx -= a.count[c];
+      ++c;
+    }
+    const ServeTickItem it = a.list[(int64_t)c * a.list_cap + idx];
+    if (!it.block) continue;
+    const ClassConst& cc = a.cc[c];
+    switch (cc.n_thr * 2 + (cc.lag ? 1 : 0)) {
+#define MG_CASE(n)                                  \
+  case 2 * n:                                       \
+    serve_page<n, false>(it, cc, a, lane);          \
+    break;                                          \
+  case 2 * n + 1:                                   \
+    serve_page<n, true>(it, cc, a, lane);           \
+    break;
+      MG_CASE(1) MG_CASE(2) MG_CASE(3) MG_CASE(4) MG_CASE(5) MG_CASE(6) MG_CASE(7) MG_CASE(8)
+#undef MG_CASE
+      default:
+        break;
+    }
   }
 }
 
-__global__ void __launch_bounds__(256) k_serve_patch(const ServePatch* __restrict__ patches,
-                                                     int32_t n, ServeTickItem* __restrict__ list) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) list[patches[i].index] = patches[i].item;
-}
-
-hipError_t launch_serve_patch(const ServePatch* patches, int32_t n, ServeTickItem* list,
-                              hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_serve_patch, dim3((n + 255) / 256), dim3(256), 0, s, patches, n, list);
-  return hipGetLastError();
-}
-
-__global__ void __launch_bounds__(64) k_serve_gather(const ServeGatherItem* __restrict__ items,
-                                                     int32_t Dmax) {
+// one block of 64 threads per finished page
+__global__ void __launch_bounds__(64) k_serve_leave(const ServeGatherItem* __restrict__ items,
+                                                    ServeTickItem* __restrict__ list,
+                                                    int32_t Dmax) {
   const ServeGatherItem it = items[blockIdx.x];
   const int lane = threadIdx.x;
+  if (lane == 0) {
+    ServeTickItem z;
+    z.block = nullptr;
+    z.cols = nullptr;
+    z.actions = nullptr;
+    z.ld = 0;
+    z.t0 = 0;
+    z.L = 0;
+    z.pad_ = 0;
+    list[it.list_index] = z;
+  }
   const int64_t col = it.cols[lane];
   if (col < 0) return;
   for (int i = 0; i < Dmax; ++i) it.out[i * it.n + col] = it.block[i * kPageEnvs + lane];
 }
 
-hipError_t launch_serve_init(const ServeInitItem* items, int32_t n_items,
+hipError_t launch_serve_join(const ServeInitItem* items, int32_t n_items, ServeTickItem* list,
                              const ClassNominal* nominal, int32_t Dmax, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_serve_init, dim3(n_items), dim3(64), 0, s, items, nominal, Dmax);
+  hipLaunchKernelGGL(k_serve_join, dim3(n_items), dim3(64), 0, s, items, list, nominal, Dmax);
   return hipGetLastError();
 }
 
-template <int N, bool LAG>
-static hipError_t tick_t(const ClassConst& cc, int32_t cls, const ServeTickItem* items,
-                         const ServeTickHeader* hdr, int32_t Dmax, int32_t n_max,
-                         int32_t substeps, float dt, int32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_serve_tick<N, LAG>), dim3(grid), dim3(kBlock), 0, s, items, hdr, cls, cc,
-                     Dmax, n_max, substeps, dt);
+hipError_t launch_serve_tick(const ServeTickArgs& a, int32_t grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_serve_tick, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_serve_tick(const ClassConst& cc, int32_t cls, const ServeTickItem* items,
-                             const ServeTickHeader* hdr, int32_t Dmax, int32_t n_max,
-                             int32_t substeps, float dt, int32_t grid, hipStream_t s) {
-  const bool lag = cc.lag != 0;
-#define MG_CASE(n)                                                                            \
-  case n:                                                                                     \
-    return lag ? tick_t<n, true>(cc, cls, items, hdr, Dmax, n_max, substeps, dt, grid, s)     \
-               : tick_t<n, false>(cc, cls, items, hdr, Dmax, n_max, substeps, dt, grid, s);
-  switch (cc.n_thr) {
-    MG_CASE(1) MG_CASE(2) MG_CASE(3) MG_CASE(4) MG_CASE(5) MG_CASE(6) MG_CASE(7) MG_CASE(8)
-    default:
-      return hipErrorInvalidValue;
-  }
-#undef MG_CASE
-}
-
-hipError_t launch_serve_gather(const ServeGatherItem* items, int32_t n_items, int32_t Dmax,
-                               hipStream_t s) {
+hipError_t launch_serve_leave(const ServeGatherItem* items, int32_t n_items, ServeTickItem* list,
+                              int32_t Dmax, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_serve_gather, dim3(n_items), dim3(64), 0, s, items, Dmax);
+  hipLaunchKernelGGL(k_serve_leave, dim3(n_items), dim3(64), 0, s, items, list, Dmax);
   return hipGetLastError();
 }
 

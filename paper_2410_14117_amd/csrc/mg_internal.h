@@ -169,6 +169,18 @@ struct AdjArgs {
 // A page is a block of (Dmax + kNumDerived) rows x 64 lanes of floats: the
 // state rows first, then the per-env derived constants; its column map gives,
 // per lane, the env's column in the request's input arrays (-1 = empty lane).
+// The per-tick item arrays (joins, leaves) live in pinned host memory that
+// the kernels read through its device mapping: a tick copies nothing to the
+// device.
+struct ServeTickItem {         // one active page (device-resident list entry)
+  float* block;                // NULL: an empty entry
+  const int32_t* cols;
+  const float* actions;        // request [L][n_max][ld]
+  int64_t ld;
+  int64_t t0;                  // control-step clock when the request joined
+  int32_t L;                   // control steps of the request
+  int32_t pad_;
+};
 struct ServeInitItem {         // one newly admitted page
   float* block;
   const int32_t* cols_src;     // staged column map of the page (64 entries)
@@ -178,39 +190,38 @@ struct ServeInitItem {         // one newly admitted page
   int64_t ld;
   int32_t cls;
   int32_t pad_;
-};
-struct ServeTickItem {         // one active page (device-resident list entry)
-  float* block;                // NULL: an empty entry
-  const int32_t* cols;
-  const float* actions;        // request [L][n_max][ld]
-  int64_t ld;
-  int64_t t0;                  // tick of the request's first control step
-};
-struct ServeTickHeader {       // per tick: entries in use per class and the tick number
-  int32_t count[16];
-  int64_t tick;
-};
-struct ServePatch {            // one write into the device-resident tick list
-  int64_t index;               // cls * capacity + entry
-  ServeTickItem item;
+  int64_t list_index;          // its tick-list entry, cls * capacity + entry,
+  ServeTickItem item;          // which receives this item
 };
 struct ServeGatherItem {       // one page of a finished request
   const float* block;
   const int32_t* cols;
   float* out;                  // device staging [Dmax][n] of the request
   int64_t n;
+  int64_t list_index;          // its tick-list entry, emptied here
 };
-hipError_t launch_serve_init(const ServeInitItem* items, int32_t n_items,
+struct ServeTickArgs {         // one tick over the pages of every class
+  const ServeTickItem* list;   // [n_classes][list_cap]
+  const ClassConst* cc;        // device [n_classes]
+  int64_t list_cap;
+  int64_t tick;                // control-step clock at the tick's start
+  int32_t count[16];           // list entries in use per class
+  int32_t n_classes;
+  int32_t steps;               // most control steps a page advances
+  int32_t Dmax, n_max, substeps;
+  float dt;
+};
+// joins: initialise each admitted page (one 64-lane block per page) and enter
+// it in the tick list
+hipError_t launch_serve_join(const ServeInitItem* items, int32_t n_items, ServeTickItem* list,
                              const ClassNominal* nominal, int32_t Dmax, hipStream_t s);
-// grid is fixed (persistent) so the launch can live in a replayed graph; the
-// number of entries and the tick number are read from the header on the device
-hipError_t launch_serve_tick(const ClassConst& cc, int32_t cls, const ServeTickItem* items,
-                             const ServeTickHeader* hdr, int32_t Dmax, int32_t n_max,
-                             int32_t substeps, float dt, int32_t grid, hipStream_t s);
-hipError_t launch_serve_patch(const ServePatch* patches, int32_t n, ServeTickItem* list,
-                              hipStream_t s);
-hipError_t launch_serve_gather(const ServeGatherItem* items, int32_t n_items, int32_t Dmax,
-                               hipStream_t s);
+// one launch advances the pages of all classes (a wave per page, persistent
+// over `grid` blocks)
+hipError_t launch_serve_tick(const ServeTickArgs& a, int32_t grid, hipStream_t s);
+// leaves: copy each finished page's states into its request's staging and
+// empty its tick-list entry
+hipError_t launch_serve_leave(const ServeGatherItem* items, int32_t n_items, ServeTickItem* list,
+                              int32_t Dmax, hipStream_t s);
 
 // launchers (kernels_adjoint.hip)
 hipError_t launch_adjoint(bool backward, const ClassConst& cc, const AdjArgs& a, hipStream_t s);

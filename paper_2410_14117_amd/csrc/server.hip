@@ -5,11 +5,17 @@
 // Requests enter a FIFO admission queue.  A scheduler thread runs ticks: it
 // admits queued requests while their pages fit under the memory cap, writes
 // their envs into 64-env single-class pages (state + per-env factorisation,
-// k_serve_init), advances every active page by one control step with one
-// persistent launch per vehicle class replayed from a HIP graph, and retires
-// finished requests (k_serve_gather, copy to the client's host buffer, pages
-// freed).  States stay on the device for the whole life of a request;
-// requests that arrive while others run join at the next tick.
+// k_serve_join), advances every active page by one or more control steps with
+// one launch over the pages of all classes (k_serve_tick), and retires
+// finished requests (k_serve_leave gathers their states, one copy brings them
+// to pinned host memory, a delivery thread copies them to the clients and
+// frees the pages).  States stay on the device for the whole life of a
+// request; requests that arrive while others run join at the next tick.  A
+// tick's item arrays are written by the host into pinned memory that the
+// kernels read through its device mapping, so a tick issues at most three
+// launches and one copy.  A tick may advance each page by up to
+// steps_per_tick control steps (as many as its request has left); the tick
+// number is then a control-step clock that moves by steps_per_tick per tick.
 #include "mg.h"
 #include "mg_internal.h"
 #include "page_pool.h"
@@ -66,22 +72,63 @@ struct Record {
   bool finished = false;
 };
 
-// Pinned host buffer + device buffer of the same capacity.  Growth keeps the
-// outgrown pair until release(): freeing device memory waits for the whole
-// device, which would stall the tick pipeline, so the scheduler never frees;
-// capacities double, so the retired pairs add up to less than the live one.
+// Pinned host buffer mapped into the device's address space: the host writes
+// it, kernels read or write it through `dev`.  It is allocated coherent
+// (fine-grained), so the device neither caches stale copies of what the host
+// rewrites for a later tick nor holds back what it writes for the host.
+// Growth keeps the outgrown
+// buffers until release(): freeing pinned memory can wait for the device,
+// which would stall the tick pipeline, so the scheduler never frees;
+// capacities double, so the retired buffers add up to less than the live one.
 template <class T>
-struct Mirror {
+struct Pinned {
   T* h = nullptr;
-  T* d = nullptr;
+  T* dev = nullptr;
   size_t cap = 0;
-  std::vector<std::pair<T*, T*>> outgrown;
+  std::vector<T*> outgrown;
   bool grow(size_t need) {
     if (need <= cap) return true;
     size_t c = std::max<size_t>(need, cap * 2 + 64);
     T *nh = nullptr, *nd = nullptr;
-    if (hipHostMalloc((void**)&nh, c * sizeof(T), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&nd, c * sizeof(T)) != hipSuccess) {
+    if (hipHostMalloc((void**)&nh, c * sizeof(T), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void**)&nd, nh, 0) != hipSuccess || !nd) {
+      (void)hipGetLastError();
+      if (nh) (void)hipHostFree(nh);
+      return false;
+    }
+    if (h) outgrown.push_back(h);
+    h = nh;
+    dev = nd;
+    cap = c;
+    return true;
+  }
+  void release() {
+    if (h) outgrown.push_back(h);
+    for (T* p : outgrown) (void)hipHostFree(p);
+    outgrown.clear();
+    h = nullptr;
+    dev = nullptr;
+    cap = 0;
+  }
+};
+
+// Result buffer of a tick: device staging that the leave kernel gathers into
+// and a pinned host buffer that one DMA copy fills (small scattered writes from
+// the device straight into host memory measured several times slower).  The
+// host side is pinned with the default flags: it is only ever read by the host
+// after the copy has completed.  Growth keeps the outgrown pairs, as Pinned.
+struct OutBuffer {
+  float* h = nullptr;
+  float* d = nullptr;
+  size_t cap = 0;
+  std::vector<std::pair<float*, float*>> outgrown;
+  bool grow(size_t need) {
+    if (need <= cap) return true;
+    size_t c = std::max<size_t>(need, cap * 2 + 64);
+    float *nh = nullptr, *nd = nullptr;
+    if (hipHostMalloc((void**)&nh, c * sizeof(float), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&nd, c * sizeof(float)) != hipSuccess) {
       (void)hipGetLastError();
       if (nh) (void)hipHostFree(nh);
       return false;
@@ -93,7 +140,7 @@ struct Mirror {
     return true;
   }
   void release() {
-    outgrown.emplace_back(h, d);
+    if (h || d) outgrown.emplace_back(h, d);
     for (auto& hd : outgrown) {
       if (hd.first) (void)hipHostFree(hd.first);
       if (hd.second) (void)hipFree(hd.second);
@@ -112,6 +159,7 @@ struct mg_server {
   int32_t D = 13, n_max = 1, substeps = 1, n_classes = 1;
   double dt = 0.005;
   bool fifo_plain = false;
+  int32_t steps_per_tick = 1;        // most control steps a page advances per tick
   int64_t max_queue = 65536;
   std::vector<ClassConst> cc;
   std::vector<ClassNominal> nominal;
@@ -130,28 +178,36 @@ struct mg_server {
     return slab_cols[p / slab_pages] + (p % slab_pages) * kPageEnvs;
   }
 
-  // ring of tick slots: each holds the staging buffers, graph and event of one
-  // tick in flight, so the host builds tick k+1 while the GPU runs tick k
+  // ring of tick slots: each holds the staging buffers and event of one tick
+  // in flight, so the host builds tick k+1 while the GPU runs tick k
   struct Slot {
-    Mirror<ServeInitItem> init;
-    Mirror<int32_t> cols_stage;
-    Mirror<ServeTickHeader> hdr;
-    Mirror<ServePatch> pre, post;    // list writes before / after this tick's kernels
-    Mirror<ServeGatherItem> gather;
-    Mirror<float>* out = nullptr;     // pooled pinned buffer of this tick's finished requests
-    hipGraphExec_t graph = nullptr;
+    Pinned<ServeInitItem> init;       // pages joining in this tick
+    Pinned<int32_t> cols_stage;       // their column maps
+    Pinned<ServeGatherItem> gather;   // pages leaving after this tick
+    OutBuffer* out = nullptr;     // pooled result buffer of this tick's finished requests
     hipEvent_t ev = nullptr;
     std::vector<Request*> retiring;   // finished by this tick, delivered on completion
   };
+  // one piece of a finished request to deliver: floats [begin, end) of its
+  // states, which sit at src in the pinned side of a tick's result buffer that
+  // the tick's finished requests share.  Large results are cut into pieces of
+  // kDeliverChunk floats that the delivery threads copy in parallel; the
+  // request completes with its last piece, and the tick's last piece returns
+  // the buffer to the pool.
   struct Delivery {
-    std::vector<Request*> reqs;
-    Mirror<float>* out;
+    Request* r;
+    const float* src;
+    size_t begin, end;
+    OutBuffer* out;
+    std::shared_ptr<std::atomic<int>> pending_req, pending_tick;
   };
+  static constexpr size_t kDeliverChunk = (size_t)1 << 18;
+  static constexpr int kDeliverThreads = 4;
   static constexpr int kSlots = 3;
   Slot slots[kSlots];
   std::deque<int> inflight;           // slot indices in issue order
   int next_slot = 0;
-  int64_t tick_no = 0;
+  int64_t tick_no = 0;                // control-step clock at the next tick's start
 
   // device-resident tick list: per class list_cap entries (a page's entry stays
   // put while its request runs); entries are reused lowest index first
@@ -159,7 +215,8 @@ struct mg_server {
   size_t list_cap = 0;
   std::vector<std::set<int32_t>> free_entries;
   std::vector<int32_t> hw;            // per class: entries in use are below hw
-  int32_t grid = 1024;
+  int32_t max_grid = 1024;            // blocks of the tick launch (4 pages each) at most
+  ClassConst* cc_dev = nullptr;       // device copy of cc
 
   // queue, records, thread
   std::mutex mu;
@@ -172,14 +229,15 @@ struct mg_server {
   bool broken = false;
   std::string err;
   std::thread thr;
-  // delivery thread: copies finished requests' states to the clients, frees their
-  // pages and completes them, off the scheduler thread
-  std::thread deliver_thr;
+  // delivery threads: copy finished requests' states to the clients, free their
+  // pages and complete them, off the scheduler thread; a few of them, so that a
+  // large result does not hold up the small ones finishing beside it
+  std::thread deliver_thr[kDeliverThreads];
   std::mutex dmu;
   std::condition_variable dcv, dcv_done;
   std::deque<Delivery> deliver_q;
-  std::vector<Mirror<float>*> out_pool;   // free pinned result buffers (guarded by dmu)
-  std::vector<Mirror<float>*> out_all;    // every result buffer, for teardown
+  std::vector<OutBuffer*> out_pool;   // free pinned result buffers (guarded by dmu)
+  std::vector<OutBuffer*> out_all;    // every result buffer, for teardown
   bool deliver_stop = false;
 
   // statistics
@@ -222,36 +280,6 @@ ClassNominal class_nominal(const mg_vehicle& v) {
   return n;
 }
 
-// (Re)captures the tick graph: one persistent launch per class (fused: one
-// control step of `substeps` sub-steps; FIFO baseline: `substeps` plain
-// launches of one sub-step), reading its items and count from fixed buffers.
-bool capture_tick_graph(mg_server* S, mg_server::Slot& sl) {
-  if (sl.graph) {
-    (void)hipGraphExecDestroy(sl.graph);
-    sl.graph = nullptr;
-  }
-  hipStream_t cap;
-  SV_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  const int reps = S->fifo_plain ? S->substeps : 1;
-  const int sub = S->fifo_plain ? 1 : S->substeps;
-  for (int r = 0; r < reps && e == hipSuccess; ++r)
-    for (int c = 0; c < S->n_classes && e == hipSuccess; ++c)
-      e = launch_serve_tick(S->cc[c], c, S->list_d + (size_t)c * S->list_cap, sl.hdr.d, S->D,
-                            S->n_max, sub, (float)S->dt, S->grid, cap);
-  hipError_t e2 = hipStreamEndCapture(cap, &g);
-  (void)hipStreamDestroy(cap);
-  if (e != hipSuccess || e2 != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return fail_server(S, "tick graph capture failed");
-  }
-  hipError_t e3 = hipGraphInstantiate(&sl.graph, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e3 != hipSuccess) return fail_server(S, "tick graph instantiate failed");
-  return true;
-}
-
 void finish(mg_server* S, Request* r, mg_status st) {
   const uint64_t t = clock_ns();
   {
@@ -266,38 +294,41 @@ void finish(mg_server* S, Request* r, mg_status st) {
   delete r;
 }
 
-// Deliver the requests that finished in a completed tick: copy their states
-// from the pinned result buffer to the clients, free their pages, complete them.
+// Deliver one piece of a request that finished in a completed tick: copy it
+// from the pinned result buffer to the client; with the request's last piece,
+// free its pages and complete it.
 void deliver(mg_server* S, mg_server::Delivery& d) {
-  size_t o = 0;
-  for (Request* r : d.reqs) {
-    std::memcpy(r->out, d.out->h + o, (size_t)r->n * S->D * sizeof(float));
-    o += (size_t)r->n * S->D;
+  Request* r = d.r;
+  std::memcpy(r->out + d.begin, d.src + d.begin, (d.end - d.begin) * sizeof(float));
+  if (d.pending_req->fetch_sub(1) == 1) {
     {
       std::lock_guard<std::mutex> lk(S->mu);
       S->pool->release(r->pages);
     }
     finish(S, r, MG_OK);
   }
-  std::lock_guard<std::mutex> lk(S->dmu);
-  S->out_pool.push_back(d.out);
+  if (d.pending_tick->fetch_sub(1) == 1) {
+    std::lock_guard<std::mutex> lk(S->dmu);
+    S->out_pool.push_back(d.out);
+  }
 }
 
-Mirror<float>* take_out_buffer(mg_server* S) {
+OutBuffer* take_out_buffer(mg_server* S) {
   std::lock_guard<std::mutex> lk(S->dmu);
   if (!S->out_pool.empty()) {
-    Mirror<float>* m = S->out_pool.back();
+    OutBuffer* m = S->out_pool.back();
     S->out_pool.pop_back();
     return m;
   }
-  S->out_all.push_back(new Mirror<float>());
+  S->out_all.push_back(new OutBuffer());
   return S->out_all.back();
 }
 
-// Mirror::grow, counting the growths that allocate (they cost host time in the
-// scheduler; the counter shows whether a run was served from warm buffers).
+// Pinned / OutBuffer::grow, counting the growths that allocate (they cost host
+// time in the scheduler; the counter shows whether a run was served from warm
+// buffers).
 template <class T>
-bool grow_counted(mg_server* S, Mirror<T>& m, size_t need) {
+bool grow_counted(mg_server* S, T& m, size_t need) {
   const size_t before = m.cap;
   const bool ok = m.grow(need);
   if (m.cap != before) S->grow_events.fetch_add(1);
@@ -305,7 +336,7 @@ bool grow_counted(mg_server* S, Mirror<T>& m, size_t need) {
 }
 
 // Grows the device tick list to hold `need` entries per class: waits for the
-// stream, copies the host mirror and re-captures every slot's graph.
+// stream and copies the host mirror into the new list.
 bool grow_list(mg_server* S, size_t need, std::vector<ServeTickItem>& host) {
   size_t cap = std::max<size_t>(need, 2 * S->list_cap + 256);
   SV_HIP(hipStreamSynchronize(S->stream));
@@ -320,19 +351,19 @@ bool grow_list(mg_server* S, size_t need, std::vector<ServeTickItem>& host) {
   S->list_d = d;
   S->list_cap = cap;
   host.swap(nh);
-  for (auto& sl : S->slots)
-    if (!capture_tick_graph(S, sl)) return false;
   return true;
 }
 
 // Enqueue one tick into a free slot: initialise admitted pages and enter them
-// in the tick list, advance every active page one control step, gather the
-// requests whose last step this is into the slot's pinned buffer and empty
-// their list entries; record the slot's event.  Host work is proportional to
-// the pages that join or leave, not to the pages in flight.
+// in the tick list, advance every active page by up to steps_per_tick control
+// steps, gather the states of the requests that finish into the slot's result
+// buffer (copied to its pinned host side) and empty their list entries; record
+// the slot's event.  Host
+// work is proportional to the pages that join or leave, not to the pages in
+// flight.
 bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admitted,
                  std::vector<ServeTickItem>& list_h) {
-  // 1. newly admitted pages: list entries first (the list may grow), then patches
+  // 1. newly admitted pages: list entries first (the list may grow), then one join launch
   size_t n_init = 0;
   for (Request* r : admitted) n_init += r->pages.size();
   if (n_init) {
@@ -354,9 +385,8 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
     size_t need = 0;
     for (int c = 0; c < S->n_classes; ++c) need = std::max<size_t>(need, S->hw[c]);
     if (need > S->list_cap && !grow_list(S, need, list_h)) return false;
-    if (!grow_counted(S, sl.init, n_init) || !grow_counted(S, sl.cols_stage, n_init * kPageEnvs) ||
-        !grow_counted(S, sl.pre, n_init))
-      return fail_server(S, "host/device staging allocation failed");
+    if (!grow_counted(S, sl.init, n_init) || !grow_counted(S, sl.cols_stage, n_init * kPageEnvs))
+      return fail_server(S, "pinned staging allocation failed");
     size_t k = 0;
     for (Request* r : admitted) {
       r->t0 = S->tick_no;
@@ -365,54 +395,68 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
         std::memcpy(sl.cols_stage.h + k * kPageEnvs, r->cols.data() + p * kPageEnvs,
                     kPageEnvs * sizeof(int32_t));
         it.block = S->page_block(r->pages[p]);
-        it.cols_src = sl.cols_stage.d + k * kPageEnvs;
+        it.cols_src = sl.cols_stage.dev + k * kPageEnvs;
         it.cols = S->page_cols(r->pages[p]);
         it.x0 = r->x0;
         it.mult = r->mult;
         it.ld = r->ld;
         it.cls = r->page_cls[p];
         it.pad_ = 0;
-        ServePatch& pt = sl.pre.h[k];
-        pt.index = (int64_t)r->page_cls[p] * (int64_t)S->list_cap + r->entry[p];
-        pt.item.block = it.block;
-        pt.item.cols = it.cols;
-        pt.item.actions = r->actions;
-        pt.item.ld = r->ld;
-        pt.item.t0 = r->t0;
-        list_h[pt.index] = pt.item;
+        it.list_index = (int64_t)r->page_cls[p] * (int64_t)S->list_cap + r->entry[p];
+        it.item.block = it.block;
+        it.item.cols = it.cols;
+        it.item.actions = r->actions;
+        it.item.ld = r->ld;
+        it.item.t0 = r->t0;
+        it.item.L = r->L;
+        it.item.pad_ = 0;
+        list_h[it.list_index] = it.item;
       }
     }
-    SV_HIP(hipMemcpyAsync(sl.cols_stage.d, sl.cols_stage.h, n_init * kPageEnvs * sizeof(int32_t),
-                          hipMemcpyHostToDevice, S->stream));
-    SV_HIP(hipMemcpyAsync(sl.init.d, sl.init.h, n_init * sizeof(ServeInitItem),
-                          hipMemcpyHostToDevice, S->stream));
-    SV_HIP(launch_serve_init(sl.init.d, (int32_t)n_init, S->nominal_dev, S->D, S->stream));
-    SV_HIP(hipMemcpyAsync(sl.pre.d, sl.pre.h, n_init * sizeof(ServePatch), hipMemcpyHostToDevice,
-                          S->stream));
-    SV_HIP(launch_serve_patch(sl.pre.d, (int32_t)n_init, S->list_d, S->stream));
+    SV_HIP(launch_serve_join(sl.init.dev, (int32_t)n_init, S->list_d, S->nominal_dev, S->D,
+                             S->stream));
     for (Request* r : admitted) S->active.push_back(r);
     admitted.clear();
   }
 
-  // 2. the tick itself
-  int64_t envs = 0;
-  for (Request* r : S->active) envs += r->n;
-  std::memset(sl.hdr.h, 0, sizeof(ServeTickHeader));
-  for (int c = 0; c < S->n_classes; ++c) sl.hdr.h->count[c] = S->hw[c];
-  sl.hdr.h->tick = S->tick_no;
-  SV_HIP(hipMemcpyAsync(sl.hdr.d, sl.hdr.h, sizeof(ServeTickHeader), hipMemcpyHostToDevice,
-                        S->stream));
-  SV_HIP(hipGraphLaunch(sl.graph, S->stream));
+  // 2. the tick itself: every page advances min(K, steps its request has left);
+  // the FIFO baseline runs S launches of one plain sub-step instead
+  const int32_t K = S->steps_per_tick;
+  int64_t envs = 0, env_steps = 0;
+  for (Request* r : S->active) {
+    envs += r->n;
+    env_steps += r->n * std::min<int64_t>(K, r->L - r->step);
+  }
+  ServeTickArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.list = S->list_d;
+  a.cc = S->cc_dev;
+  a.list_cap = (int64_t)S->list_cap;
+  a.tick = S->tick_no;
+  int64_t total = 0;
+  for (int c = 0; c < S->n_classes; ++c) {
+    a.count[c] = S->hw[c];
+    total += S->hw[c];
+  }
+  a.n_classes = S->n_classes;
+  a.steps = K;
+  a.Dmax = S->D;
+  a.n_max = S->n_max;
+  a.substeps = S->fifo_plain ? 1 : S->substeps;
+  a.dt = (float)S->dt;
+  const int32_t grid = (int32_t)std::min<int64_t>(S->max_grid, std::max<int64_t>(1, (total + 3) / 4));
+  const int reps = S->fifo_plain ? S->substeps : 1;
+  for (int rep = 0; rep < reps; ++rep) SV_HIP(launch_serve_tick(a, grid, S->stream));
   S->active_envs.store(envs);
   if (envs > S->max_active_envs.load()) S->max_active_envs.store(envs);
-  S->env_steps.fetch_add(envs);
+  S->env_steps.fetch_add(env_steps);
   S->ticks.fetch_add(1);
-  ++S->tick_no;
+  S->tick_no += K;
 
-  // 3. the requests whose last control step this was
+  // 3. the requests whose last control step was in this tick
   std::vector<Request*> keep;
   for (Request* r : S->active) {
-    ++r->step;
+    r->step += (int32_t)std::min<int64_t>(K, r->L - r->step);
     (r->step >= r->L ? sl.retiring : keep).push_back(r);
   }
   S->active.swap(keep);
@@ -423,22 +467,19 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
   }
   if (!sl.retiring.empty()) {
     sl.out = take_out_buffer(S);
-    if (!grow_counted(S, sl.gather, n_gat) || !grow_counted(S, *sl.out, n_out) ||
-        !grow_counted(S, sl.post, n_gat))
-      return fail_server(S, "gather staging allocation failed");
+    if (!grow_counted(S, sl.gather, n_gat) || !grow_counted(S, *sl.out, n_out))
+      return fail_server(S, "pinned result allocation failed");
     size_t k = 0, o = 0;
     for (Request* r : sl.retiring) {
       for (size_t p = 0; p < r->pages.size(); ++p, ++k) {
         ServeGatherItem& it = sl.gather.h[k];
+        const int32_t c = r->page_cls[p];
         it.block = S->page_block(r->pages[p]);
         it.cols = S->page_cols(r->pages[p]);
         it.out = sl.out->d + o;
         it.n = r->n;
-        ServePatch& pt = sl.post.h[k];
-        const int32_t c = r->page_cls[p];
-        pt.index = (int64_t)c * (int64_t)S->list_cap + r->entry[p];
-        std::memset(&pt.item, 0, sizeof(pt.item));
-        list_h[pt.index] = pt.item;
+        it.list_index = (int64_t)c * (int64_t)S->list_cap + r->entry[p];
+        std::memset(&list_h[it.list_index], 0, sizeof(ServeTickItem));
         S->free_entries[c].insert(r->entry[p]);
       }
       o += (size_t)r->n * S->D;
@@ -451,14 +492,9 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
         --S->hw[c];
       }
     }
-    SV_HIP(hipMemcpyAsync(sl.gather.d, sl.gather.h, n_gat * sizeof(ServeGatherItem),
-                          hipMemcpyHostToDevice, S->stream));
-    SV_HIP(launch_serve_gather(sl.gather.d, (int32_t)n_gat, S->D, S->stream));
+    SV_HIP(launch_serve_leave(sl.gather.dev, (int32_t)n_gat, S->list_d, S->D, S->stream));
     SV_HIP(hipMemcpyAsync(sl.out->h, sl.out->d, n_out * sizeof(float), hipMemcpyDeviceToHost,
                           S->stream));
-    SV_HIP(hipMemcpyAsync(sl.post.d, sl.post.h, n_gat * sizeof(ServePatch), hipMemcpyHostToDevice,
-                          S->stream));
-    SV_HIP(launch_serve_patch(sl.post.d, (int32_t)n_gat, S->list_d, S->stream));
   }
   SV_HIP(hipEventRecord(sl.ev, S->stream));
   return true;
@@ -477,11 +513,25 @@ bool retire_oldest(mg_server* S, bool block, bool* took) {
   if (e != hipSuccess) return fail_server(S, std::string("tick: ") + hipGetErrorString(e));
   S->inflight.pop_front();
   if (!sl.retiring.empty()) {
-    std::lock_guard<std::mutex> lk(S->dmu);
-    S->deliver_q.push_back(mg_server::Delivery{std::move(sl.retiring), sl.out});
+    const size_t C = mg_server::kDeliverChunk;
+    int pieces = 0;
+    for (Request* r : sl.retiring) pieces += (int)(((size_t)r->n * S->D + C - 1) / C);
+    auto pending_tick = std::make_shared<std::atomic<int>>(pieces);
+    {
+      std::lock_guard<std::mutex> lk(S->dmu);
+      size_t o = 0;
+      for (Request* r : sl.retiring) {
+        const size_t len = (size_t)r->n * S->D;
+        auto pending_req = std::make_shared<std::atomic<int>>((int)((len + C - 1) / C));
+        for (size_t b = 0; b < len; b += C)
+          S->deliver_q.push_back(mg_server::Delivery{r, sl.out->h + o, b, std::min(len, b + C),
+                                                     sl.out, pending_req, pending_tick});
+        o += len;
+      }
+    }
     sl.retiring.clear();
     sl.out = nullptr;
-    S->dcv.notify_one();
+    S->dcv.notify_all();
   }
   *took = true;
   return true;
@@ -583,7 +633,8 @@ void scheduler(mg_server* S) {
     S->deliver_stop = true;
   }
   S->dcv.notify_all();
-  if (S->deliver_thr.joinable()) S->deliver_thr.join();
+  for (auto& t : S->deliver_thr)
+    if (t.joinable()) t.join();
   for (int k : S->inflight) {
     for (Request* r : S->slots[k].retiring) finish(S, r, st);
     S->slots[k].retiring.clear();
@@ -622,6 +673,10 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
     return bad(MG_ERR_INVALID, "n_classes outside 1..16 or classes NULL");
   if (!(cfg->dt_sub > 0.0) || cfg->substeps < 1) return bad(MG_ERR_INVALID, "dt_sub / substeps");
   if (cfg->reserve_bytes < 0) return bad(MG_ERR_INVALID, "reserve_bytes < 0");
+  if (cfg->steps_per_tick < 0 || cfg->steps_per_tick > 64)
+    return bad(MG_ERR_INVALID, "steps_per_tick outside 0..64");
+  if (cfg->fifo_plain && cfg->steps_per_tick > 1)
+    return bad(MG_ERR_INVALID, "the FIFO plain baseline takes one control step per tick");
   for (int k = 0; k < cfg->n_classes; ++k) {
     const mg_vehicle& v = cfg->classes[k];
     if (v.n_thr < 1 || v.n_thr > MG_MAX_THRUSTERS || (v.thr_map != 0 && v.thr_map != 1) ||
@@ -644,6 +699,7 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   S->substeps = cfg->substeps;
   S->dt = cfg->dt_sub;
   S->fifo_plain = cfg->fifo_plain != 0;
+  S->steps_per_tick = cfg->steps_per_tick > 1 ? cfg->steps_per_tick : 1;
   S->max_queue = cfg->max_queue > 0 ? cfg->max_queue : 65536;
   for (int k = 0; k < cfg->n_classes; ++k) {
     const mg_vehicle& v = cfg->classes[k];
@@ -682,6 +738,9 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
       hipMalloc(&S->nominal_dev, sizeof(ClassNominal) * S->n_classes) != hipSuccess ||
       hipMemcpy(S->nominal_dev, S->nominal.data(), sizeof(ClassNominal) * S->n_classes,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMalloc(&S->cc_dev, sizeof(ClassConst) * S->n_classes) != hipSuccess ||
+      hipMemcpy(S->cc_dev, S->cc.data(), sizeof(ClassConst) * S->n_classes,
                 hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
     mg_server_destroy(S.release());
@@ -702,8 +761,7 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
     }
   }
   for (auto& sl : S->slots) {
-    if (!sl.hdr.grow(1) || hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
-        !capture_tick_graph(S.get(), sl)) {
+    if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
       mg_server_destroy(S.release());
       return bad(MG_ERR_DEVICE, "tick slot initialisation failed");
@@ -716,12 +774,12 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
     const size_t items = (size_t)std::min<int64_t>(4096, S->pool->created_pages());
     for (auto& sl : S->slots)
       ok = ok && sl.init.grow(items) && sl.cols_stage.grow(items * kPageEnvs) &&
-           sl.pre.grow(items) && sl.post.grow(items) && sl.gather.grow(items);
+           sl.gather.grow(items);
     // result buffers: one per slot in flight plus those the delivery thread
     // still copies out of (large outputs arriving in bursts), 16 MB each
     const size_t out_floats = std::min<size_t>(items * kPageEnvs * (size_t)S->D, (size_t)1 << 22);
     for (int i = 0; ok && i < 16; ++i) {
-      S->out_all.push_back(new Mirror<float>());
+      S->out_all.push_back(new OutBuffer());
       S->out_pool.push_back(S->out_all.back());
       ok = S->out_all.back()->grow(out_floats);
     }
@@ -730,7 +788,7 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
       return bad(MG_ERR_OOM, "could not reserve the requested page memory and staging");
     }
   }
-  S->deliver_thr = std::thread(deliverer, S.get());
+  for (auto& t : S->deliver_thr) t = std::thread(deliverer, S.get());
   S->thr = std::thread(scheduler, S.get());
   *out = S.release();
   return MG_OK;
@@ -855,20 +913,17 @@ void mg_server_destroy(mg_server* S) {
     S->deliver_stop = true;
   }
   S->dcv.notify_all();
-  if (S->deliver_thr.joinable()) S->deliver_thr.join();
+  for (auto& t : S->deliver_thr)
+    if (t.joinable()) t.join();
   (void)hipSetDevice(S->device);
   if (S->stream) (void)hipStreamSynchronize(S->stream);
   for (auto& sl : S->slots) {
-    if (sl.graph) (void)hipGraphExecDestroy(sl.graph);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
     sl.init.release();
     sl.cols_stage.release();
-    sl.hdr.release();
-    sl.pre.release();
-    sl.post.release();
     sl.gather.release();
   }
-  for (Mirror<float>* m : S->out_all) {
+  for (OutBuffer* m : S->out_all) {
     m->release();
     delete m;
   }
@@ -876,6 +931,7 @@ void mg_server_destroy(mg_server* S) {
   for (float* b : S->slab_blocks) (void)hipFree(b);
   for (int32_t* c : S->slab_cols) (void)hipFree(c);
   if (S->nominal_dev) (void)hipFree(S->nominal_dev);
+  if (S->cc_dev) (void)hipFree(S->cc_dev);
   if (S->stream) (void)hipStreamDestroy(S->stream);
   (void)hipGetLastError();
   delete S;

@@ -12,7 +12,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MG_LIBRARY") or os.path.join(HERE, "libmg.so")
 
-MG_ABI_VERSION = 2
+MG_ABI_VERSION = 3
 MAX_THR = 8
 NUM_PARAMS = 23
 NUM_THETA = 19
@@ -56,6 +56,7 @@ class MgServerConfig(ctypes.Structure):
         ("mem_cap_bytes", ctypes.c_int64), ("mem_fraction", ctypes.c_double),
         ("fifo_plain", ctypes.c_int32), ("max_queue", ctypes.c_int32),
         ("reserve_bytes", ctypes.c_int64),
+        ("steps_per_tick", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -450,7 +451,7 @@ class Server:
     """Continuous-batching serving loop on one GPU (wraps an ``mg_server``)."""
 
     def __init__(self, classes, dt_sub, substeps, device=0, mem_cap_bytes=0, mem_fraction=0.0,
-                 fifo_plain=False, max_queue=0, reserve_bytes=0):
+                 fifo_plain=False, max_queue=0, reserve_bytes=0, steps_per_tick=1):
         import threading
         L = lib()
         if isinstance(classes, dict):
@@ -468,6 +469,7 @@ class Server:
         cfg.fifo_plain = 1 if fifo_plain else 0
         cfg.max_queue = int(max_queue)
         cfg.reserve_bytes = int(reserve_bytes)
+        cfg.steps_per_tick = int(steps_per_tick)
         h = _vp()
         st = L.mg_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if st != MG_OK:

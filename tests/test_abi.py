@@ -96,3 +96,32 @@ def test_create_without_device_reports_device_error():
     c, _keep = _cfg(BLUEROV2)
     assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_DEVICE
     assert h.value is None
+
+
+def _server_cfg(preset, **kw):
+    v = (mg.MgVehicle * 1)(mg.vehicle_struct(preset))
+    c = mg.MgServerConfig()
+    c.abi_version = kw.get("abi_version", mg.MG_ABI_VERSION)
+    c.n_classes = 1
+    c.classes = v
+    c.dt_sub = 0.005
+    c.substeps = kw.get("substeps", 4)
+    c.device = 0
+    c.fifo_plain = kw.get("fifo_plain", 0)
+    c.reserve_bytes = kw.get("reserve_bytes", 0)
+    c.steps_per_tick = kw.get("steps_per_tick", 1)
+    return c, v
+
+
+def test_server_create_rejects_bad_config():
+    """Malformed server configurations fail with MG_ERR_INVALID before any device work."""
+    from workloads import BLUEROV2
+    L = mg.lib()
+    h = ctypes.c_void_p()
+    assert L.mg_server_create(None, ctypes.byref(h)) == mg.MG_ERR_INVALID
+    for kw in [dict(abi_version=2), dict(substeps=0), dict(reserve_bytes=-1),
+               dict(steps_per_tick=-1), dict(steps_per_tick=65),
+               dict(fifo_plain=1, steps_per_tick=2)]:
+        c, _keep = _server_cfg(BLUEROV2, **kw)
+        assert L.mg_server_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_INVALID, kw
+        assert h.value is None

@@ -116,6 +116,28 @@ def test_fifo_plain_baseline_same_results(mgmod, pools):
         assert rel_err(v, u) <= 1e-5
 
 
+@pytest.mark.parametrize("K", [8, 64])
+def test_steps_per_tick_same_results(mgmod, pools, K):
+    """Pages advanced by up to K control steps per tick (as many as their request has left)
+    end in the same states, bitwise, as with one step per tick: requests of 1 to 64 steps,
+    most not a multiple of K, joining while others run; the same env-steps in fewer ticks."""
+    say("serve steps per tick", K)
+    reqs = [R, (50, 300, 7), (9000, 4100, 3), (20000, 700, 64), (15000, 2000, 1),
+            (30000, 64, 9), (31000, 65, 17), (33000, 3000, 63)]
+    a = mgmod.Server(CLASSES, DT, S)
+    outs_a, _ = _serve(a, pools, reqs)
+    st_a = a.stats()
+    a.close()
+    b = mgmod.Server(CLASSES, DT, S, steps_per_tick=K)
+    outs_b, _ = _serve(b, pools, reqs)
+    st_b = b.stats()
+    b.close()
+    for u, v in zip(outs_a, outs_b):
+        np.testing.assert_array_equal(u, v)
+    assert st_a["env_steps"] == st_b["env_steps"] == sum(n * L for _, n, L in reqs)
+    assert st_b["ticks"] < st_a["ticks"]
+
+
 def test_memory_cap_admission(mgmod, pools):
     """A 20-page cap: requests wait for pages instead of failing; a request larger than the
     whole cap is rejected at submit; no more pages than the cap are ever created."""

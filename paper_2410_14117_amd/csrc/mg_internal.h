@@ -160,9 +160,11 @@ struct AdjArgs {
   float* gact;                 // caller [T][n_max][E]
   float* gtheta;               // caller [19][E]
   float* gx0;                  // caller [D][E] or NULL
-  float* segbuf;               // internal [K * S][Dc][Ep] scratch (Dc = class state width)
+  float* segbuf;               // internal [K * S][Dc][Ep] scratch (Dc = class state width),
+                               // or [T * S][Dc][Ep] when recomputed
   float zb;                    // class z_b (for dL/dB through h_z)
   int32_t n_cu;                // compute units (picks the backward kernel's occupancy)
+  int32_t recomputed;          // segbuf already holds every sub-step input of the rollout
 };
 
 // ---- serving loop (kernels_serve.hip) -------------------------------------
@@ -225,6 +227,8 @@ hipError_t launch_serve_leave(const ServeGatherItem* items, int32_t n_items, Ser
 
 // launchers (kernels_adjoint.hip)
 hipError_t launch_adjoint(bool backward, const ClassConst& cc, const AdjArgs& a, hipStream_t s);
+// every segment's sub-step inputs at once, into the whole-rollout segbuf
+hipError_t launch_adj_recompute(const ClassConst& cc, const AdjArgs& a, hipStream_t s);
 
 // launchers (kernels_step.hip)
 hipError_t launch_step(const ClassConst& cc, const StepArgs& a, hipStream_t s);

@@ -860,7 +860,17 @@ mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* actions, in
   if (!dL_dtraj || !dL_dact || !dL_dtheta)
     return fail(s, MG_ERR_INVALID, "dL_dtraj, dL_dact and dL_dtheta must not be NULL");
   DeviceGuard g(s->device);
-  const size_t need = (size_t)std::min(ckpt_every, T) * s->substeps * s->D * (size_t)s->Ep;
+  // A sparse launch (no more envs than one wave per SIMD across the device)
+  // recomputes every segment at once into a whole-rollout buffer (at most
+  // 1 GiB), so that the backward sweep does not wait for each segment's
+  // recomputation in turn; otherwise each segment is recomputed just before
+  // its sweep into a segment-sized buffer.
+  const int32_t nseg = (T + ckpt_every - 1) / ckpt_every;
+  const size_t whole_floats = (size_t)T * s->substeps * s->D * (size_t)s->Ep;
+  const bool whole = nseg > 1 && nseg <= 65535 && s->E <= (int64_t)s->n_cu * 4 * 64 &&
+                     whole_floats * sizeof(float) <= ((size_t)1 << 30);
+  const size_t need = whole ? whole_floats
+                            : (size_t)std::min(ckpt_every, T) * s->substeps * s->D * (size_t)s->Ep;
   if (need > s->segbuf_cap) {
     MG_HIP(s, hipStreamSynchronize(s->stream));
     if (s->segbuf) MG_HIP(s, hipFree(s->segbuf));
@@ -880,10 +890,12 @@ mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* actions, in
   a.gtheta = dL_dtheta;
   a.gx0 = dL_dx0;
   a.segbuf = s->segbuf;
+  a.recomputed = whole ? 1 : 0;
   for (int k = 0; k < s->n_classes; ++k) {
     a.seg_start = s->seg_start[k];
     a.seg_len = s->seg_len[k];
     a.zb = (float)s->nominal[k].zb;
+    if (whole) MG_HIP(s, launch_adj_recompute(s->cc[k], a, s->stream));
     MG_HIP(s, launch_adjoint(true, s->cc[k], a, s->stream));
   }
   return MG_OK;

@@ -231,3 +231,32 @@ def test_crowded_backward_variant(mgmod, oracle):
         assert _rel(g_act[:, :, e], r_act[:, :, k]) <= TOL_GRAD
         assert _rel(g_th[:, e], r_th[:, k]) <= TOL_GRAD
         assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD
+
+
+@pytest.mark.parametrize("n_thr,lag", [(1, False), (1, True), (3, True), (5, False), (7, True),
+                                       (8, False)])
+def test_other_instantiations(mgmod, oracle, n_thr, lag):
+    """Thruster counts and lag settings the other tests leave out (each is its own compiled
+    kernel pair): 257 envs, 7 control steps of 3 sub-steps, checkpoints every 3, against the
+    oracle's dual-number gradient on 9 envs including the ragged tail."""
+    v = dict(vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05 if lag else 0.0))
+    v["thr_pos"] = v["thr_pos"][:n_thr]
+    v["thr_dir"] = v["thr_dir"][:n_thr]
+    D = 13 + (n_thr if lag else 0)
+    E, T, K, S, dt = 257, 7, 3, 3, 0.005
+    x0 = initial_state(E, D, 351)
+    if lag:
+        x0[13:] = np.random.default_rng(352).uniform(-20, 20, size=(n_thr, E)).astype(np.float32)
+    act = actions(T, n_thr, E, 353) * np.float32(1.1)
+    mult = param_multipliers(E, 0.2, 354)
+    pref, qref = circle_waypoints(T, E, 0.02, 355)
+    say(f"adjoint instantiation N={n_thr} lag={lag}")
+    _, g_act, g_th, g_x0, _ = _gpu_grads(mgmod, v, x0, act, mult, pref, qref, S, dt, K)
+    sub = np.r_[0:256:37, 255, 256]
+    _, r_act, r_th, r_x0 = oracle.track_loss_grad(
+        v, x0[:, sub], act[:, :, sub], S, dt, pref[:, :, sub], qref[:, :, sub],
+        mult=mult[:, sub], want_x0=True)
+    for k, e in enumerate(sub):
+        assert _rel(g_act[:, :, e], r_act[:, :, k]) <= TOL_GRAD
+        assert _rel(g_th[:, e], r_th[:, k]) <= TOL_GRAD
+        assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD

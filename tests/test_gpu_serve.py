@@ -138,6 +138,45 @@ def test_steps_per_tick_same_results(mgmod, pools, K):
     assert st_b["ticks"] < st_a["ticks"]
 
 
+def test_other_class_instantiations(mgmod, pools):
+    """A server of three classes with 5 thrusters without lag, 7 with lag and 2 with lag
+    (instantiations of the tick kernel the other tests leave out): each request's states
+    equal those of mg_step, bitwise."""
+    base = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
+    classes = []
+    for n_thr, tau in ((5, 0.0), (7, 0.05), (2, 0.05)):
+        v = dict(base)
+        v["thr_pos"] = v["thr_pos"][:n_thr]
+        v["thr_dir"] = v["thr_dir"][:n_thr]
+        v["thr_tau"] = tau
+        classes.append(v)
+    n = 3000
+    cls = (np.arange(n) * 7 % 3).astype(np.int32)
+    x0 = initial_state(n, 20, 411)
+    x0[13:, cls == 0] = 0
+    x0[15:, cls == 2] = 0
+    act = actions(12, 7, n, 412)
+    mult = param_multipliers(n, 0.2, 413)
+    x0_d, act_d, mult_d = dev(x0), dev(act), dev(mult)
+    say("serve three classes")
+    srv = mgmod.Server(classes, DT, S, steps_per_tick=4)
+    outs = []
+    for L, lo, hi in ((12, 0, 1000), (5, 1000, 3000)):
+        out = np.zeros((20, hi - lo), np.float32)
+        st, t = srv.submit(hi - lo, L, x0_d.data_ptr() + 4 * lo, act_d.data_ptr() + 4 * lo, n, out,
+                           env_class=cls[lo:hi], mult_ptr=mult_d.data_ptr() + 4 * lo)
+        assert st == 0
+        outs.append((t, out, L, lo, hi))
+    for t, out, L, lo, hi in outs:
+        assert srv.wait(t, 60_000_000)[0] == 0
+        sim = mgmod.Sim(classes, hi - lo, DT, S, env_class=cls[lo:hi])
+        sim.reset(state=dev(x0[:, lo:hi]), param_mult=dev(mult[:, lo:hi]))
+        sim.step(dev(act[:L, :, lo:hi]))
+        np.testing.assert_array_equal(host(sim.get_state()), out)
+        sim.close()
+    srv.close()
+
+
 def test_memory_cap_admission(mgmod, pools):
     """A 20-page cap: requests wait for pages instead of failing; a request larger than the
     whole cap is rejected at submit; no more pages than the cap are ever created."""

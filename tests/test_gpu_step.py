@@ -512,3 +512,22 @@ def test_largest_env_count_offsets_beyond_32_bits(mgmod, oracle):
     got[19:, c == 0] = 0.0
     ref = oracle.rollout(classes, xs, acts, S, dt, env_class=c, mult=ms)
     assert rel_err(got, ref["x"]) <= TOL_ONE_STEP
+
+
+@pytest.mark.parametrize("n_thr,lag", [(2, False), (5, False), (7, True), (8, False)])
+def test_other_instantiations(mgmod, oracle, n_thr, lag):
+    """Thruster counts and lag settings the other step tests leave out (each is its own
+    compiled kernel): 300 envs, one control step and 20 steps of 4 sub-steps vs the oracle."""
+    v = dict(vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05 if lag else 0.0))
+    v["thr_pos"] = v["thr_pos"][:n_thr]
+    v["thr_dir"] = v["thr_dir"][:n_thr]
+    D = 13 + (n_thr if lag else 0)
+    E = 300
+    x0 = random_states(E, D, 81)
+    act = actions(20, n_thr, E, 82) * np.float32(1.2)
+    mult = param_multipliers(E, 0.2, 83)
+    say("step instantiation", n_thr, lag)
+    tr, st, _ = _run(mgmod, v, x0, act, 0.005, 4, mult=mult)
+    ref = oracle.rollout(v, x0, act, 4, 0.005, mult=mult, want_traj=True)
+    assert rel_err(tr[0], ref["traj"][0]) <= TOL_ONE_STEP
+    assert rel_err(tr, ref["traj"]) <= 1e-4

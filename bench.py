@@ -191,8 +191,9 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
     BlueROV2 / Heavy (+-20 % randomisation, 4 RK4 sub-steps of 5 ms per control step),
     inputs resident on the device; latency = arrival -> final states in host memory.  The
     server creates `reserve_bytes` of page memory at start, and a warm-up trace of
-    `warmup_s` (another seed) runs first on it, so that the timed trace finds its pages,
-    staging buffers and tick graphs allocated."""
+    `warmup_s` (another seed) runs first on it, so that the timed trace finds its pages and
+    staging buffers allocated.  `steps_per_tick`: most control steps a request advances
+    per tick."""
     import threading
     from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
                            actions, param_multipliers, env_classes)

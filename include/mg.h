@@ -294,9 +294,9 @@ mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, 
  * requests.  Continuous batching: a scheduler thread admits queued requests
  * FIFO whenever their pages (64 envs of one class each) fit under the memory
  * cap, keeps their states on the device, and advances every admitted request
- * by one control step per tick with one persistent launch per vehicle class
- * replayed from a HIP graph; a request that arrives while others run joins at
- * the next tick, and a finished one frees its pages at once.  Each env goes
+ * by up to steps_per_tick control steps per tick with one launch over the
+ * pages of all vehicle classes; a request that arrives while others run joins
+ * at the next tick, and a finished one frees its pages at once.  Each env goes
  * through exactly the arithmetic of mg_step, so a request's result does not
  * depend on what else is in flight.
  *

@@ -217,9 +217,10 @@ k_adj_bwd(const AdjArgs a, const ClassConst cc) {
 }
 
 // Every segment's recomputation at once (blockIdx.y = segment) into the
-// whole-rollout buffer, ahead of a backward launch with a.recomputed: when the
-// backward launch has few waves, its segments' recomputations, independent of
-// one another, then cost one segment's latency instead of all of them.
+// whole-rollout buffer, ahead of a backward launch with a.recomputed: the
+// segments' recomputations, independent of one another, then cost one
+// segment's latency when the backward launch has few waves, and the sweep
+// kernel carries no recomputation registers when it has many.
 template <int N, bool LAG>
 __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_recompute(const AdjArgs a,
                                                                          const ClassConst cc) {
@@ -271,7 +272,10 @@ static hipError_t launch_adj_t(bool backward, const ClassConst& cc, const AdjArg
   if (nblk == 0) return hipSuccess;
   // one wave per SIMD over the whole device: n_cu CUs x 4 SIMDs x 64 lanes
   const bool crowded = a.seg_len > (int64_t)a.n_cu * 4 * 64;
-  if (backward && a.recomputed)
+  if (backward && a.recomputed && crowded)
+    hipLaunchKernelGGL((k_adj_bwd<N, LAG, 2, true>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a,
+                       cc);
+  else if (backward && a.recomputed)
     hipLaunchKernelGGL((k_adj_bwd<N, LAG, 1, true>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a,
                        cc);
   else if (backward && crowded)

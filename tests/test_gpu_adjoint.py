@@ -202,9 +202,11 @@ def test_mixed_classes_interleaved(mgmod, oracle):
 
 def test_crowded_backward_variant(mgmod, oracle):
     """A class segment with more envs than one wave per SIMD across the device takes the
-    backward kernel built for two waves per SIMD (registers squeezed, some spilled): its
-    gradients equal, bitwise, those of the one-wave kernel on a small launch of the same envs,
-    and match the oracle on a sample that includes the ragged tail."""
+    backward kernels built for two waves per SIMD (registers squeezed, some spilled), both the
+    sweep over a whole-rollout recomputation (checkpoints every 3 steps) and the one that
+    recomputes its single segment itself (checkpoint every 6): their gradients equal, bitwise,
+    those of the one-wave kernel on a small launch of the same envs, and match the oracle on a
+    sample that includes the ragged tail."""
     v = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     E, T, K, S, dt = n_cu * 4 * 64 + 3 * 64 + 37, 6, 3, 2, 0.005
@@ -215,6 +217,11 @@ def test_crowded_backward_variant(mgmod, oracle):
     pref, qref = circle_waypoints(T, E, 0.02, 345)
     say(f"crowded adjoint E={E}")
     _, g_act, g_th, g_x0, _ = _gpu_grads(mgmod, v, x0, act, mult, pref, qref, S, dt, K)
+    say(f"crowded adjoint E={E}, one segment")
+    _, h_act, h_th, h_x0, _ = _gpu_grads(mgmod, v, x0, act, mult, pref, qref, S, dt, T)
+    np.testing.assert_array_equal(h_act, g_act)
+    np.testing.assert_array_equal(h_th, g_th)
+    np.testing.assert_array_equal(h_x0, g_x0)
     small = np.r_[0:2048, E - 2048:E]
     say(f"one-wave adjoint E={small.size}")
     _, s_act, s_th, s_x0, _ = _gpu_grads(mgmod, v, x0[:, small], act[:, :, small],

@@ -273,9 +273,13 @@ mg_status mg_task_counters(mg_sim* sim, int32_t* out);
  *   ckpt     device [ceil(T / ckpt_every)][D][E]  (written)
  *   traj     device [T][D][E] state after each control step, or NULL
  * mg_adj_backward: given dL/d traj, recomputes each segment of ckpt_every
- *   control steps from its checkpoint (memory O(T / ckpt_every) states plus
- *   one segment of sub-steps, held in a scratch buffer the sim owns) and
- *   sweeps it backwards.
+ *   control steps from its checkpoint and sweeps it backwards.  The sub-step
+ *   states it linearises about are held in a scratch buffer the sim owns and
+ *   keeps until mg_destroy: the whole rollout's (T * substeps * D * E floats)
+ *   when that fits in 4 GiB and there is more than one segment, every segment
+ *   then recomputed at once before the sweep; otherwise one segment's
+ *   (ckpt_every * substeps * D * E floats), recomputed just before its sweep.
+ *   The gradients are the same, bitwise, either way.
  *   ckpt, actions  as written / read by mg_adj_forward with the same T, ckpt_every
  *   dL_dtraj  device [T][D][E]
  *   dL_dact   device [T][N_max][E]  (written; rows >= a class's n_thr are 0,

@@ -288,3 +288,59 @@ def test_poisson_clients_all_complete(mgmod, pools):
     srv.close()
     assert 0 < np.percentile(lats, 50) <= np.percentile(lats, 99) < 30
     assert rng is not None
+
+
+@pytest.mark.slow
+def test_c5_trace_in_the_benchmark_configuration(mgmod):
+    """The benchmark's serving configuration (8 control steps per tick, 2 GiB reserved, 32
+    Poisson clients at 2000 req/s for 0.3 s, env counts log-uniform in [16, 65536], half step
+    requests and half rollouts of 1..64 steps, mixed classes): every request completes with
+    finite states, and 12 of them (the largest, the longest and 10 at random) equal mg_step's
+    result bitwise."""
+    P = 1 << 17
+    cls = env_classes(P, "bernoulli", 421)
+    x0 = initial_state(P, D, 422)
+    x0[19:, cls == 0] = 0
+    mult = param_multipliers(P, 0.2, 423)
+    act = actions(LMAX, NMAX, P, 424)
+    x0_d, mult_d, act_d = dev(x0), dev(mult), dev(act)
+    rng = np.random.default_rng(425)
+    trace = []
+    for k in range(32):
+        t = 0.0
+        while True:
+            t += rng.exponential(32 / 2000.0)
+            if t > 0.3:
+                break
+            n = int(round(np.exp(rng.uniform(np.log(16), np.log(65536)))))
+            L = 1 if rng.random() < 0.5 else int(rng.integers(1, LMAX + 1))
+            trace.append((t, n, L, int(rng.integers(0, P - n + 1))))
+    trace.sort()
+    say(f"serve c5 configuration, {len(trace)} requests")
+    srv = mgmod.Server(CLASSES, DT, S, steps_per_tick=8, reserve_bytes=2 << 30)
+    t0 = mgmod.Server.clock_ns() + 20_000_000
+    subs = []
+    for t, n, L, off in trace:
+        at = t0 + int(t * 1e9)
+        while mgmod.Server.clock_ns() < at:
+            time.sleep(0.0002)
+        out = np.zeros((D, n), np.float32)
+        st, tk = srv.submit(n, L, x0_d.data_ptr() + 4 * off, act_d.data_ptr() + 4 * off, P, out,
+                            env_class=cls[off:off + n], mult_ptr=mult_d.data_ptr() + 4 * off,
+                            arrival_ns=at)
+        assert st == 0
+        subs.append((tk, out, n, L, off))
+    for tk, out, n, L, off in subs:
+        assert srv.wait(tk, 60_000_000)[0] == 0
+        assert np.isfinite(out).all()
+    srv.close()
+    pick = {int(np.argmax([s[2] for s in subs])), int(np.argmax([s[3] for s in subs]))}
+    pick |= set(int(i) for i in rng.choice(len(subs), 10, replace=False))
+    for i in sorted(pick):
+        _, out, n, L, off = subs[i]
+        c = cls[off:off + n]
+        sim = mgmod.Sim(CLASSES, n, DT, S, env_class=c)
+        sim.reset(state=dev(x0[:, off:off + n]), param_mult=dev(mult[:, off:off + n]))
+        sim.step(dev(act[:L, :, off:off + n]))
+        np.testing.assert_array_equal(host(sim.get_state()), out)
+        sim.close()

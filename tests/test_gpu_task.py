@@ -245,3 +245,38 @@ def test_task_step_captured_in_a_graph(mgmod):
         _ = torch.ones(1000, device="cuda").sum()     # eager work between replays
     eager.close()
     capt.close()
+
+
+@pytest.mark.slow
+def test_full_size_circle_task_sampled(mgmod, oracle):
+    """The benchmark's task configuration: 2^20 envs (half BlueROV2, half Heavy), 16 sub-steps
+    of 5 ms per control step, circle tracking with 4 look-ahead points, episodes of 100.
+    After 3 task steps every counter is 3, no env is done, and the observation of 256 envs
+    spread over both classes (and the last env) equals the oracle's of the GPU's own state."""
+    E, S16, T = 1 << 20, 16, 3
+    cls = env_classes(E, "halves")
+    x0 = initial_state(E, D, 901)
+    x0[19:, cls == 0] = 0
+    g = torch.Generator(device="cuda").manual_seed(902)
+    act = torch.rand((T, 8, E), generator=g, device="cuda") * 2 - 1
+    phase = (np.random.default_rng(903).uniform(0, 2 * math.pi, E)).astype(np.float32)
+    center = np.zeros((3, E), np.float32)
+    tk = {"task": "circle", "lookahead": 4, "radius": 2.0, "omega": 0.5, "episode_steps": 100}
+    say("task full size circle")
+    sim = mgmod.Sim(CLASSES, E, DT, S16, env_class=cls)
+    sim.reset(state=dev(x0))
+    sim.task_configure(tk, dev(center), dev(phase))
+    for t in range(T):
+        obs, err, done = sim.task_step(act[t])
+    torch.cuda.synchronize()
+    k = host(sim.task_counters())
+    assert np.all(k == T)
+    assert int(done.abs().sum()) == 0 and bool(torch.isfinite(err).all())
+    idx = np.unique(np.r_[np.linspace(0, E - 1, 256).astype(np.int64), E - 1])
+    it = torch.from_numpy(idx).to("cuda")
+    got = host(obs[:, it])
+    x = host(sim.get_state()[:, it])
+    sim.close()
+    ref = oracle.task_observe(tk, x, center[:, idx], phase[idx], np.zeros(idx.size, np.float32),
+                              k[idx], S16 * DT)
+    assert _obs_err(got, ref) <= 1e-6

@@ -267,3 +267,43 @@ def test_other_instantiations(mgmod, oracle, n_thr, lag):
         assert _rel(g_act[:, :, e], r_act[:, :, k]) <= TOL_GRAD
         assert _rel(g_th[:, e], r_th[:, k]) <= TOL_GRAD
         assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD
+
+
+@pytest.mark.slow
+def test_full_size_adjoint_sampled(mgmod, oracle):
+    """The benchmark's large adjoint configuration: 2^20 BlueROV2 envs (nominal, linear map,
+    no lag), 64 control steps of 10 ms, checkpoints every 8 -- the whole-rollout recompute
+    and the two-wave sweep.  Gradients of 17 envs spread over the range (and the last) match
+    the oracle's dual-number gradients."""
+    from paper_2410_14117_amd.autograd import rollout
+    E, T, K, S, dt = 1 << 20, 64, 8, 1, 0.01
+    v = BLUEROV2
+    x0 = initial_state(E, 13, 361)
+    g = torch.Generator(device="cuda").manual_seed(362)
+    act = torch.rand((T, 6, E), generator=g, device="cuda") * 2 - 1
+    pref = torch.randn((T, 3, E), generator=g, device="cuda") * 0.1
+    qref = torch.randn((T, 4, E), generator=g, device="cuda")
+    qref = qref / qref.norm(dim=1, keepdim=True)
+    say("adjoint full size")
+    sim = mgmod.Sim(v, E, dt, S)
+    params = torch.from_numpy(_nominal(v).astype(np.float32)).cuda()[:, None].expand(23, E)
+    x0_t = dev(x0).requires_grad_(True)
+    a_t = act.clone().requires_grad_(True)
+    hydro = params[4:].contiguous().requires_grad_(True)
+    traj = rollout(sim, x0_t, a_t, hydro, params[:4].contiguous(), ckpt_every=K)
+    loss = _track_loss_torch(traj, pref, qref)
+    loss.backward()
+    torch.cuda.synchronize()
+    idx = np.unique(np.r_[np.linspace(0, E - 1, 16).astype(np.int64), E - 1])
+    it = torch.from_numpy(idx).to("cuda")
+    g_act, g_th, g_x0 = host(a_t.grad[:, :, it]), host(hydro.grad[:, it]), host(x0_t.grad[:, it])
+    acts, prefs, qrefs = host(act[:, :, it]), host(pref[:, :, it]), host(qref[:, :, it])
+    del traj, loss, a_t, x0_t, hydro
+    sim.close()
+    torch.cuda.empty_cache()
+    _, r_act, r_th, r_x0 = oracle.track_loss_grad(
+        v, x0[:, idx], acts, S, dt, prefs, qrefs, mult=np.ones((23, idx.size)), want_x0=True)
+    for k in range(idx.size):
+        assert _rel(g_act[:, :, k], r_act[:, :, k]) <= TOL_GRAD
+        assert _rel(g_th[:, k], r_th[:, k]) <= TOL_GRAD
+        assert _rel(g_x0[:, k], r_x0[:, k]) <= TOL_GRAD

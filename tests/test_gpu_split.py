@@ -115,3 +115,34 @@ def test_reset_clears_the_carried_acceleration(mgmod):
     np.testing.assert_array_equal(host(a.get_state()), host(b.get_state()))
     a.close()
     b.close()
+
+
+@pytest.mark.slow
+def test_full_size_split_sampled(mgmod, oracle):
+    """The benchmark's split configuration with the added mass scaled by 0.4 (stable): 2^20
+    envs (half BlueROV2, half Heavy), 16 sub-steps of 5 ms per control step, 10 control steps
+    in one launch per class; 128 envs spread over both classes (and the last) follow the
+    oracle's split scheme within 1e-4 and every env stays finite."""
+    E, T, S16 = 1 << 20, 10, 16
+    classes = [_light_added_mass(v) for v in LAGGED]
+    cls = env_classes(E, "halves")
+    x0 = initial_state(E, D, 931)
+    x0[19:, cls == 0] = 0
+    mult = param_multipliers(E, 0.2, 932)
+    g = torch.Generator(device="cuda").manual_seed(933)
+    act = torch.rand((T, 8, E), generator=g, device="cuda") * 2 - 1
+    say("split full size")
+    sim = mgmod.Sim(classes, E, DT, S16, env_class=cls)
+    sim.reset(state=dev(x0), param_mult=dev(mult))
+    sim.step_split(act)
+    out = sim.get_state()
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
+    idx = np.unique(np.r_[np.linspace(0, E - 1, 128).astype(np.int64), E - 1])
+    it = torch.from_numpy(idx).to("cuda")
+    got = host(out[:, it])
+    acts = host(act[:, :, it])
+    sim.close()
+    ref = oracle.split_rollout(classes, x0[:, idx], acts, S16, DT, env_class=cls[idx],
+                               mult=mult[:, idx])
+    assert rel_err(got, ref["x"]) <= 1e-4

@@ -862,11 +862,11 @@ mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* actions, in
   DeviceGuard g(s->device);
   // When the rollout's sub-step inputs fit in 4 GiB, every segment is
   // recomputed at once into a whole-rollout buffer and the backward only
-  // sweeps: a sparse launch then waits for one segment's recomputation instead
-  // of each in turn (c4: backward 0.32 -> 0.26 ms), and a crowded one runs a
-  // sweep kernel without the recomputation's registers (2^20 envs: 5.1 ->
-  // 4.8 ms).  Otherwise each segment is recomputed just before its sweep into
-  // a segment-sized buffer.
+  // sweeps: a sparse launch then waits for one segment's recomputation
+  // instead of each in turn (8192 envs, 64 control steps: backward 0.32 ->
+  // 0.26 ms), and a crowded one runs a sweep kernel without the
+  // recomputation's registers (2^20 envs: 5.1 -> 4.8 ms).  Otherwise each
+  // segment is recomputed just before its sweep into a segment-sized buffer.
   const int32_t nseg = (T + ckpt_every - 1) / ckpt_every;
   const size_t whole_floats = (size_t)T * s->substeps * s->D * (size_t)s->Ep;
   const bool whole = nseg > 1 && nseg <= 65535 &&

@@ -721,6 +721,18 @@ def main():
             "frac_hbm": bytes_rollout / (plain_ms * 1e-3) / PEAK_HBM,
             "speedup_fused_vs_plain": plain_ms / fused_ms,
         }
+        # the same 6400 launches issued one by one from the host (mg_step_plain, no graph)
+        sim.reset(state=x0, param_mult=mult)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        sim.step(act, stats=stats, plain=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        eager_ms = ev0.elapsed_time(ev1)
+        out["plain"]["uncaptured"] = {
+            "env_steps_per_s": env_substeps / (eager_ms * 1e-3), "ms_per_rollout": eager_ms,
+            "avg_launch_us": eager_ms * 1e3 / (2 * T * S),
+            "frac_hbm": bytes_rollout / (eager_ms * 1e-3) / PEAK_HBM}
     if not args.no_task:
         out["task_epilogue"] = bench_task(torch, sim, act, x0, n_b, n_h)
     if not args.no_split:

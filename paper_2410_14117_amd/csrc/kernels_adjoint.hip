@@ -92,15 +92,32 @@ __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_fwd(const AdjArg
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
+  // each control step's throttles are loaded one step ahead, so that their
+  // latency hides behind the current step's sub-steps (a launch with few waves
+  // per SIMD has nothing else to hide it behind)
+  const float* abase = a.actions + c;
+  const int64_t frame = (int64_t)a.n_max * a.E;
+  float nxt[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) nxt[i] = abase[i * a.E];
   for (int t = 0; t < a.T; ++t) {
+    float act[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) act[i] = nxt[i];
+    if (t + 1 < a.T) {
+      const float* af = abase + (int64_t)(t + 1) * frame;
+#pragma unroll
+      for (int i = 0; i < N; ++i) nxt[i] = af[i * a.E];
+    }
     if (t % a.ckpt_every == 0) {
       float* ck = a.ckpt + (int64_t)(t / a.ckpt_every) * a.D * a.E + c;
 #pragma unroll
       for (int i = 0; i < D; ++i) ck[i * a.E] = x[i];
       for (int i = D; i < a.D; ++i) ck[i * a.E] = 0.0f;
     }
-    float act[N], fcmd[N], gcmd[6];
-    load_command<N>(cc, a, t, c, act, fcmd, gcmd);
+    float fcmd[N], gcmd[6];
+    thrust_command<N>(cc, act, fcmd);
+    command_wrench<N>(cc, fcmd, gcmd);
     control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, a.substeps, cc.rho_s);
     if (a.traj) {
       float* tf = a.traj + (int64_t)t * a.D * a.E + c;

@@ -72,15 +72,27 @@ def plain_bytes(n_thr, lag):
     return 4 * (2 * D + n_thr + 23)
 
 
-def kernel_source_hash():
-    """Hash of the sources the step kernels are compiled from (their traffic and counters
-    in profiles/ hold only while these are unchanged)."""
+def source_hash(files):
+    """Hash of the named files of paper_2410_14117_amd/csrc (a profile summary records the
+    hash of the sources its kernels are compiled from)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2410_14117_amd", "csrc")
-    for f in ("kernels_step.hip", "fossen_device.h", "mg_internal.h"):
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+STEP_SOURCES = ("kernels_step.hip", "fossen_device.h", "mg_internal.h")
+ADJOINT_SOURCES = ("kernels_adjoint.hip", "fossen_adjoint.h", "fossen_device.h", "mg_internal.h")
+SERVE_SOURCES = ("kernels_serve.hip", "server.hip", "fossen_device.h", "mg_internal.h")
+SPLIT_TASK_SOURCES = ("kernels_split.hip", "kernels_task.hip", "fossen_device.h", "mg_internal.h")
+
+
+def kernel_source_hash():
+    """Hash of the sources the step kernels are compiled from (their traffic and counters
+    in profiles/ hold only while these are unchanged)."""
+    return source_hash(STEP_SOURCES)
 
 
 def load_traffic(kernel_key):

@@ -276,10 +276,11 @@ mg_status mg_task_counters(mg_sim* sim, int32_t* out);
  *   control steps from its checkpoint and sweeps it backwards.  The sub-step
  *   states it linearises about are held in a scratch buffer the sim owns and
  *   keeps until mg_destroy: the whole rollout's (T * substeps * D * E floats)
- *   when that fits in 4 GiB and there is more than one segment, every segment
- *   then recomputed at once before the sweep; otherwise one segment's
- *   (ckpt_every * substeps * D * E floats), recomputed just before its sweep.
- *   The gradients are the same, bitwise, either way.
+ *   when that fits in 4 GiB, there is more than one segment and the allocation
+ *   succeeds, every segment then recomputed at once before the sweep;
+ *   otherwise one segment's (ckpt_every * substeps * D * E floats), recomputed
+ *   just before its sweep.  The gradients are the same, bitwise, either way.
+ *   MG_ERR_OOM only when the segment-sized buffer cannot be allocated.
  *   ckpt, actions  as written / read by mg_adj_forward with the same T, ckpt_every
  *   dL_dtraj  device [T][D][E]
  *   dL_dact   device [T][N_max][E]  (written; rows >= a class's n_thr are 0,

@@ -866,24 +866,38 @@ mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* actions, in
   // instead of each in turn (8192 envs, 64 control steps: backward 0.32 ->
   // 0.26 ms), and a crowded one runs a sweep kernel without the
   // recomputation's registers (2^20 envs: 5.1 -> 4.8 ms).  Otherwise each
-  // segment is recomputed just before its sweep into a segment-sized buffer.
+  // segment is recomputed just before its sweep into a segment-sized buffer;
+  // so is every segment when the whole-rollout buffer cannot be allocated.
   const int32_t nseg = (T + ckpt_every - 1) / ckpt_every;
   const size_t whole_floats = (size_t)T * s->substeps * s->D * (size_t)s->Ep;
-  const bool whole = nseg > 1 && nseg <= 65535 &&
-                     whole_floats * sizeof(float) <= ((size_t)4 << 30);
-  const size_t need = whole ? whole_floats
-                            : (size_t)std::min(ckpt_every, T) * s->substeps * s->D * (size_t)s->Ep;
-  if (need > s->segbuf_cap) {
+  const size_t seg_floats = (size_t)std::min(ckpt_every, T) * s->substeps * s->D * (size_t)s->Ep;
+  bool whole = nseg > 1 && nseg <= 65535 && whole_floats * sizeof(float) <= ((size_t)4 << 30);
+  if (whole && whole_floats > s->segbuf_cap) {
+    // the new buffer is allocated before the old one is released, so that a
+    // failure leaves the old one in place
+    MG_HIP(s, hipStreamSynchronize(s->stream));
+    float* nb = nullptr;
+    if (hipMalloc(&nb, whole_floats * sizeof(float)) == hipSuccess) {
+      float* old = s->segbuf;
+      s->segbuf = nb;
+      s->segbuf_cap = whole_floats;
+      if (old) MG_HIP(s, hipFree(old));
+    } else {
+      (void)hipGetLastError();
+      whole = false;
+    }
+  }
+  if (!whole && seg_floats > s->segbuf_cap) {
     MG_HIP(s, hipStreamSynchronize(s->stream));
     if (s->segbuf) MG_HIP(s, hipFree(s->segbuf));
     s->segbuf = nullptr;
     s->segbuf_cap = 0;
-    if (hipMalloc(&s->segbuf, need * sizeof(float)) != hipSuccess) {
+    if (hipMalloc(&s->segbuf, seg_floats * sizeof(float)) != hipSuccess) {
       (void)hipGetLastError();
       s->segbuf = nullptr;
       return fail(s, MG_ERR_OOM, "adjoint scratch allocation failed");
     }
-    s->segbuf_cap = need;
+    s->segbuf_cap = seg_floats;
   }
   AdjArgs a = adj_args(s, actions, T, ckpt_every);
   a.ckpt = const_cast<float*>(ckpt);

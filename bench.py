@@ -385,8 +385,8 @@ def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16, graph=Fals
     (30-256-128-64, ELU; FP32, random init) read the observation, Gaussian actions are
     sampled and clamped, mg_task_step advances every env, and observation, action, reward
     (-error) and done go into a rollout buffer of `horizon` steps, all on the GPU.  The
-    learner's update is not part of it.  graph=True captures one step (policy, sampling,
-    mg_task_step, buffer writes at a device-side slot index) in a HIP graph and replays it."""
+    learner's update is not part of it.  graph=True captures the step once per rollout slot
+    (policy, sampling, mg_task_step, buffer writes) in HIP graphs and replays them in turn."""
     from workloads import BLUEROV2_HEAVY, vehicle_variant, initial_state
     dev = torch.device("cuda:0")
     E, N = n_envs, 8
@@ -414,62 +414,51 @@ def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16, graph=Fals
     buf_val = torch.empty((horizon, E), device=dev)
     buf_rew = torch.empty((horizon, E), device=dev)
     buf_done = torch.empty((horizon, E), dtype=torch.int32, device=dev)
-    obs = sim.task_observe()
     err = torch.empty((E,), device=dev)
     done = torch.empty((E,), dtype=torch.int32, device=dev)
-    nxt = torch.empty_like(obs)
+    # the observation ping-pongs between two buffers: step i reads obs_pair[i % 2]
+    # and writes obs_pair[(i + 1) % 2] (horizon is even, so slot h fixes the roles)
+    obs_pair = [sim.task_observe(), None]
+    obs_pair[1] = torch.empty_like(obs_pair[0])
 
-    def one(i):
-        nonlocal obs, nxt
-        h = i % horizon
+    def one(h):
+        src, dst = obs_pair[h % 2], obs_pair[(h + 1) % 2]
         with torch.no_grad():
-            o = obs.t()
+            o = src.t()
             buf_obs[h].copy_(o)
             mu = actor(o)
             a = (mu + torch.randn_like(mu) * log_std.exp()).clamp_(-1.0, 1.0)
             buf_act[h].copy_(a)
             buf_val[h].copy_(critic(o).squeeze(1))
-            sim.task_step(a.t().contiguous(), nxt, err, done, reset_state=x0)
+            sim.task_step(a.t().contiguous(), dst, err, done, reset_state=x0)
             torch.neg(err, out=buf_rew[h])
             buf_done[h].copy_(done)
-        obs, nxt = nxt, obs
-
-    slot = torch.zeros((1,), dtype=torch.int64, device=dev)
-
-    def one_static():
-        # the same step on fixed buffers, the rollout slot kept on the device
-        with torch.no_grad():
-            o = obs.t()
-            buf_obs.index_copy_(0, slot, o.unsqueeze(0))
-            mu = actor(o)
-            a = (mu + torch.randn_like(mu) * log_std.exp()).clamp_(-1.0, 1.0)
-            buf_act.index_copy_(0, slot, a.unsqueeze(0))
-            buf_val.index_copy_(0, slot, critic(o).squeeze(1).unsqueeze(0))
-            sim.task_step(a.t().contiguous(), nxt, err, done, reset_state=x0)
-            buf_rew.index_copy_(0, slot, torch.neg(err).unsqueeze(0))
-            buf_done.index_copy_(0, slot, done.unsqueeze(0))
-            obs.copy_(nxt)
-            slot.add_(1).remainder_(horizon)
 
     if graph:
+        # one graph per rollout slot, captured in slot order into one memory pool
+        # and replayed in that order: the same work as the eager step
         s_side = torch.cuda.Stream()
         s_side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s_side):
-            for _ in range(3):
-                one_static()
+            for h in range(4):
+                one(h)
         torch.cuda.current_stream().wait_stream(s_side)
         torch.cuda.synchronize()
-        g_step = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g_step):
-            one_static()
-        run = lambda i: g_step.replay()      # noqa: E731
+        pool = torch.cuda.graph_pool_handle()
+        graphs = []
+        for h in range(horizon):
+            g_h = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g_h, pool=pool):
+                one(h)
+            graphs.append(g_h)
+        run = lambda i: graphs[i % horizon].replay()      # noqa: E731
     else:
-        run = one
+        run = lambda i: one(i % horizon)                    # noqa: E731
     for i in range(warmup):
         run(i)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
+    for i in range(warmup, warmup + steps):
         run(i)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -477,7 +466,8 @@ def bench_policy(torch, mg, n_envs, steps=100, warmup=10, horizon=16, graph=Fals
     return {"workload": f"{E} BlueROV2 Heavy envs, circle task (30 observation rows), actor + "
                         "critic MLP 30-256-128-64 (FP32), Gaussian actions, rollout buffer "
                         f"of {horizon} steps",
-            "issued": "one HIP graph replay per step" if graph else "eagerly from Python",
+            "issued": "one HIP graph replay per step (one graph per rollout slot)" if graph
+                      else "eagerly from Python",
             "n_envs": E, "steps": steps, "ms_per_step": wall * 1e3 / steps,
             "env_steps_per_s": E * steps / wall,
             "sim_seconds_per_wall_second": E * steps * 4 * 0.005 / wall}

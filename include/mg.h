@@ -86,7 +86,7 @@ typedef struct {
 
 /* Simulator description.
  *   abi_version  must be MG_ABI_VERSION
- *   n_envs       number of environments E (>= 1)
+ *   n_envs       number of environments E (1 .. 2^30 - 1024)
  *   classes      host array of n_classes (1..MG_MAX_CLASSES) vehicles
  *   env_class    host [n_envs] class index per env, or NULL (all class 0);
  *                envs are regrouped internally so that every wavefront holds

@@ -161,6 +161,54 @@ __device__ __forceinline__ void set_env_params(const ClassNominal& nom, const fl
   for (int i = 0; i < kNumDerived; ++i) derived[i * Ep + j] = dvf[i];
 }
 
+// Row-plus-lane addressing for the step kernel.  A row pointer that is the
+// same for the whole wave is pinned in scalar registers (the empty asm keeps
+// the compiler from folding the lane's offset into it), and the lane's byte
+// offset (below 4 GiB: at most 2^30 envs) is added as a 32-bit vector offset,
+// so each load or store is one global_load / global_store with an SGPR base
+// and no 64-bit index arithmetic per access.  Only wave-uniform pointers may
+// be passed as `row`.
+template <class T>
+__device__ __forceinline__ T* pin_sgpr(T* p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(v));
+  return reinterpret_cast<T*>(v);
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T& lane_elem(T* row, uint32_t off) {
+  using G = __attribute__((address_space(1))) char;
+  G* b = (G*)(pin_sgpr(row));
+  return *(__attribute__((address_space(1))) T*)(b + off);
+}
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T& lane_elem(const T* row,
+                                                                                uint32_t off) {
+  using G = const __attribute__((address_space(1))) char;
+  G* b = (G*)(pin_sgpr(row));
+  return *(const __attribute__((address_space(1))) T*)(b + off);
+}
+
+__device__ __forceinline__ EnvConst load_env_const_off(const float* __restrict__ der, int64_t Ep,
+                                                       uint32_t off) {
+  EnvConst P;
+  P.Muu = lane_elem(der + kMuu * Ep, off); P.Mvv = lane_elem(der + kMvv * Ep, off);
+  P.Mww = lane_elem(der + kMww * Ep, off); P.Mpp = lane_elem(der + kMpp * Ep, off);
+  P.Mqq = lane_elem(der + kMqq * Ep, off); P.Mrr = lane_elem(der + kMrr * Ep, off);
+  P.Muq = lane_elem(der + kMuq * Ep, off); P.Mvp = lane_elem(der + kMvp * Ep, off);
+  P.Iuu = lane_elem(der + kIuu * Ep, off); P.Ivv = lane_elem(der + kIvv * Ep, off);
+  P.Iww = lane_elem(der + kIww * Ep, off); P.Ipp = lane_elem(der + kIpp * Ep, off);
+  P.Iqq = lane_elem(der + kIqq * Ep, off); P.Irr = lane_elem(der + kIrr * Ep, off);
+  P.Iuq = lane_elem(der + kIuq * Ep, off); P.Ivp = lane_elem(der + kIvp * Ep, off);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    P.dl[i] = lane_elem(der + (kDL + i) * Ep, off);
+    P.dq[i] = lane_elem(der + (kDQ + i) * Ep, off);
+  }
+  P.wmb = lane_elem(der + kWmB * Ep, off);
+  P.hz = lane_elem(der + kHz * Ep, off);
+  return P;
+}
+
 template <int N, bool LAG>
 struct Dims {
   static constexpr int D = 13 + (LAG ? N : 0);

@@ -60,32 +60,38 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool active = local < a.seg_len;
   const int64_t j = a.seg_start + (active ? local : 0);
-  const int64_t c = active ? (a.perm ? (int64_t)a.perm[j] : j) : 0;
+  // byte offsets of the lane's env in internal and caller rows (rows of at most
+  // 2^30 floats, checked by the launcher): every access below is a wave-uniform
+  // row pointer plus this 32-bit offset, which the compiler addresses as an
+  // SGPR base plus a VGPR offset, with no per-access 64-bit index arithmetic
+  const uint32_t jo = (uint32_t)j * 4u;
+  const int64_t c = active ? (a.perm ? (int64_t)lane_elem(a.perm, jo) : j) : 0;
+  const uint32_t co = (uint32_t)c * 4u;
 
   float x[D];
   EnvConst P;
   if (active) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) x[i] = a.state[i * a.Ep + j];
-    P = load_env_const(a.derived, a.Ep, j);
+    for (int i = 0; i < D; ++i) x[i] = lane_elem(a.state + i * a.Ep, jo);
+    P = load_env_const_off(a.derived, a.Ep, jo);
   }
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
   for (int t = 0; t < n_ctrl; ++t) {
     double s_dist = 0.0, m_dist = 0.0, s_ke = 0.0, n_bad = 0.0;
     if (active) {
-      const float* af = a.actions + (int64_t)t * a.n_max * a.E + c;
+      const float* af = a.actions + (int64_t)t * a.n_max * a.E;
       float act[N], fcmd[N], gcmd[6];
 #pragma unroll
-      for (int i = 0; i < N; ++i) act[i] = af[i * a.E];
+      for (int i = 0; i < N; ++i) act[i] = lane_elem(af + i * a.E, co);
       thrust_command<N>(cc, act, fcmd);
       command_wrench<N>(cc, fcmd, gcmd);
       control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, substeps, PLAIN ? cc.rho : cc.rho_s);
       if (a.traj) {
-        float* tf = a.traj + (int64_t)t * a.D * a.E + c;
+        float* tf = a.traj + (int64_t)t * a.D * a.E;
 #pragma unroll
-        for (int i = 0; i < D; ++i) tf[i * a.E] = x[i];
-        for (int i = D; i < a.D; ++i) tf[i * a.E] = 0.0f;
+        for (int i = 0; i < D; ++i) lane_elem(tf + i * a.E, co) = x[i];
+        for (int i = D; i < a.D; ++i) lane_elem(tf + i * a.E, co) = 0.0f;
       }
       if (a.partials) {
         bool finite = true;
@@ -94,9 +100,9 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
         if (finite) {
           float tx = 0.f, ty = 0.f, tz = 0.f;
           if (a.targets) {
-            tx = a.targets[c];
-            ty = a.targets[a.E + c];
-            tz = a.targets[2 * a.E + c];
+            tx = lane_elem(a.targets, co);
+            ty = lane_elem(a.targets + a.E, co);
+            tz = lane_elem(a.targets + 2 * a.E, co);
           }
           const double dx = (double)x[0] - tx, dy = (double)x[1] - ty, dz = (double)x[2] - tz;
           s_dist = sqrt(dx * dx + dy * dy + dz * dz);
@@ -121,7 +127,7 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
   }
   if (active) {
 #pragma unroll
-    for (int i = 0; i < D; ++i) a.state[i * a.Ep + j] = x[i];
+    for (int i = 0; i < D; ++i) lane_elem(a.state + i * a.Ep, jo) = x[i];
   }
 }
 
@@ -129,6 +135,8 @@ template <int N, bool LAG>
 static hipError_t launch_step_t(const ClassConst& cc, const StepArgs& a, hipStream_t s) {
   const int64_t nblk = (a.seg_len + kBlock - 1) / kBlock;
   if (nblk == 0) return hipSuccess;
+  // 32-bit lane offsets (mg_create caps n_envs below 2^30)
+  if (a.Ep > ((int64_t)1 << 30) || a.E > ((int64_t)1 << 30)) return hipErrorInvalidValue;
   if (a.n_ctrl == 1 && a.substeps == 1)
     hipLaunchKernelGGL((k_step<N, LAG, true>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a, cc);
   else

@@ -443,8 +443,11 @@ mg_status mg_create(const mg_config* cfg, mg_sim** out) {
   *out = nullptr;
   if (!cfg) return fail(nullptr, MG_ERR_INVALID, "cfg is NULL");
   if (cfg->abi_version != MG_ABI_VERSION) return fail(nullptr, MG_ERR_INVALID, "ABI version mismatch");
-  if (cfg->n_envs < 1 || cfg->n_envs > ((int64_t)1 << 31) - 1024)
-    return fail(nullptr, MG_ERR_INVALID, "n_envs outside 1 .. 2^31 - 1024");
+  // at most 2^30 - 1024 envs, so that a padded row of floats stays below 4 GiB
+  // and the step kernel addresses it with 32-bit lane offsets (2^30 envs would
+  // not fit in device memory anyway: about 296 bytes each)
+  if (cfg->n_envs < 1 || cfg->n_envs > ((int64_t)1 << 30) - 1024)
+    return fail(nullptr, MG_ERR_INVALID, "n_envs outside 1 .. 2^30 - 1024");
   if (cfg->n_classes < 1 || cfg->n_classes > MG_MAX_CLASSES || !cfg->classes)
     return fail(nullptr, MG_ERR_INVALID, "n_classes outside 1..16 or classes NULL");
   if (!(cfg->dt_sub > 0.0) || !std::isfinite(cfg->dt_sub) || cfg->substeps < 1)

@@ -60,6 +60,10 @@ def test_create_rejects_bad_arguments():
         assert h.value is None
     c, _keep = _cfg(BLUEROV2, n_envs=0)
     assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_INVALID
+    # rows of at most 2^30 floats: the step kernel addresses them with 32-bit offsets
+    c, _keep = _cfg(BLUEROV2, n_envs=(1 << 30) - 1023)
+    assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_INVALID
+    assert b"2^30" in L.mg_last_error(None)
     bad = vehicle_variant(BLUEROV2, thr_map=3)
     c, _keep = _cfg(bad)
     assert L.mg_create(ctypes.byref(c), ctypes.byref(h)) == mg.MG_ERR_INVALID

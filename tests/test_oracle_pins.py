@@ -437,6 +437,122 @@ def test_batched_classes_equal_separate_runs_and_threads(oracle):
 
 
 # --------------------------------------------------------------------------------------
+# circle-tracking loss of the adjoint workload: sum over control steps t = 1..T of
+# |p_t - p*_t|^2 + lam (1 - <q_t, q*_t>^2), x_t the state after control step t
+# --------------------------------------------------------------------------------------
+
+def _neutral_vehicle(**kw):
+    """CG at the CB (r_g = r_b = 0) and B = W: no restoring wrench at any attitude."""
+    return vehicle_variant(BLUEROV2, r_g=[0.0, 0.0, 0.0], **kw)
+
+
+def _axis_angle_quat(axis, angle):
+    n = np.asarray(axis, dtype=float)
+    n = n / np.linalg.norm(n)
+    return np.concatenate([[math.cos(angle / 2)], math.sin(angle / 2) * n])
+
+
+def _hold(T, arr):
+    """[k][E] -> the same reference at every one of T control steps, [T][k][E]."""
+    return np.repeat(np.asarray(arr, dtype=float)[None], T, axis=0)
+
+
+def _random_unit_quats(E, seed):
+    q = np.random.default_rng(seed).normal(size=(4, E))
+    return q / np.linalg.norm(q, axis=0)
+
+
+def test_tracking_loss_zero_on_a_held_reference(oracle):
+    """At rest with no restoring wrench and zero throttle a vehicle stays put; with the
+    reference at its own pose every term vanishes.  Each term is >= 0, so a zero sum over
+    the T steps means zero at every step."""
+    v = _neutral_vehicle()
+    E, T = 6, 7
+    rng = np.random.default_rng(31)
+    x0 = np.zeros((13, E))
+    x0[0:3] = rng.uniform(-3, 3, size=(3, E))
+    x0[3:7] = _random_unit_quats(E, 32)
+    act = np.zeros((T, 6, E))
+    traj = oracle.rollout(v, x0, act, 1, 0.01, want_traj=True)["traj"]
+    np.testing.assert_allclose(traj, _hold(T, x0), rtol=0, atol=1e-15)   # the premise
+    for lam in (1.0, 0.7):
+        loss = oracle.track_loss(v, x0, act, 1, 0.01, _hold(T, x0[0:3]), _hold(T, x0[3:7]),
+                                 lam=lam)
+        np.testing.assert_allclose(loss, 0.0, rtol=0, atol=1e-14)
+
+
+def test_tracking_loss_offsets_closed_form(oracle):
+    """A held pose offset by d in position and by a rotation of angle delta about any axis
+    from the reference: <q, q*> = cos(delta / 2), so each step adds
+    |d|^2 + lam sin^2(delta / 2) and the loss is T times that."""
+    v = _neutral_vehicle()
+    T, lam = 9, 0.7
+    deltas = np.array([0.0, 0.3, -1.2, 2.5, math.pi, 4.0, 0.9, -2.2])
+    axes = [(0, 0, 1)] * 6 + [(1, 0, 0), (0.3, -0.5, 0.8)]    # yaw-only, roll, oblique
+    E = len(deltas)
+    rng = np.random.default_rng(41)
+    p0 = rng.uniform(-2, 2, size=(3, E))
+    d = rng.normal(0.0, 0.5, size=(3, E))
+    d[:, 0] = 0.0                                               # a pure attitude offset
+    qref = _random_unit_quats(E, 42)
+    x0 = np.zeros((13, E))
+    x0[0:3] = p0
+    for e in range(E):
+        # state attitude = reference rotated by delta about a body axis: q = q* (x) r
+        x0[3:7, e] = _qmul(qref[:, e], _axis_angle_quat(axes[e], deltas[e]))
+    act = np.zeros((T, 6, E))
+    loss = oracle.track_loss(v, x0, act, 1, 0.01, _hold(T, p0 - d), _hold(T, qref), lam=lam)
+    expect = T * (np.sum(d * d, axis=0) + lam * np.sin(deltas / 2) ** 2)
+    np.testing.assert_allclose(loss, expect, rtol=1e-13, atol=1e-14)
+    assert expect[4] == pytest.approx(T * (np.sum(d[:, 4] ** 2) + lam), rel=1e-15)
+
+
+def test_tracking_loss_sign_of_quaternion_is_irrelevant(oracle):
+    """q and -q are the same attitude: negating the initial quaternion negates the whole
+    attitude trajectory (R(q) is quadratic, q' linear in q), and negating the reference
+    quaternions changes no term, on a randomised rollout with every force acting."""
+    x0, act, pref, qref, mult = _c4_small(E=6, T=10)
+    base = oracle.track_loss(BLUEROV2, x0, act, 1, 0.01, pref, qref, mult=mult)
+    x0n = x0.astype(np.float64).copy()
+    x0n[3:7] *= -1.0
+    np.testing.assert_allclose(oracle.track_loss(BLUEROV2, x0n, act, 1, 0.01, pref, qref,
+                                                 mult=mult), base, rtol=1e-14)
+    qn = qref.astype(np.float64).copy()
+    qn[::2] *= -1.0                                  # every other step's reference
+    np.testing.assert_allclose(oracle.track_loss(BLUEROV2, x0, act, 1, 0.01, pref, qn,
+                                                 mult=mult), base, rtol=1e-14)
+    assert np.all(base > 0)
+
+
+def test_tracking_loss_counts_the_states_after_each_control_step(oracle):
+    """Undamped coasting with no restoring wrench: surge u0 at yaw psi0 keeps nu constant
+    (C(nu) nu = 0 for nu along one principal axis), so after control step t of S sub-steps
+    p_t = p0 + t S dt u0 (cos psi0, sin psi0, 0).  Against a reference held at the origin
+    the loss is sum_{t=1..T} |p0 + t c|^2, and a reference moving with the vehicle gives 0."""
+    v = _neutral_vehicle(d_lin=[0.0] * 6, d_quad=[0.0] * 6)
+    T, S, dt = 12, 4, 0.005
+    psi0 = np.array([0.0, 0.8, -2.4])
+    u0 = np.array([0.8, -1.5, 0.3])
+    E = len(psi0)
+    p0 = np.array([[0.5, -1.0, 2.0], [0.2, 0.3, -0.7], [-0.4, 1.1, 0.05]])
+    x0 = np.zeros((13, E))
+    x0[0:3] = p0
+    x0[3] = np.cos(psi0 / 2)
+    x0[6] = np.sin(psi0 / 2)
+    x0[7] = u0
+    act = np.zeros((T, 6, E))
+    c = u0 * S * dt * np.stack([np.cos(psi0), np.sin(psi0), np.zeros(E)])   # [3][E] per step
+    t = np.arange(1, T + 1)
+    expect = (T * np.sum(p0 * p0, axis=0) + 2 * np.sum(p0 * c, axis=0) * t.sum()
+              + np.sum(c * c, axis=0) * (t * t).sum())
+    loss = oracle.track_loss(v, x0, act, S, dt, np.zeros((T, 3, E)), _hold(T, x0[3:7]))
+    np.testing.assert_allclose(loss, expect, rtol=1e-13)
+    moving = p0[None] + t[:, None, None] * c[None]
+    loss = oracle.track_loss(v, x0, act, S, dt, moving, _hold(T, x0[3:7]))
+    np.testing.assert_allclose(loss, 0.0, atol=1e-20)
+
+
+# --------------------------------------------------------------------------------------
 # reference gradient (dual numbers) vs finite differences and a closed form
 # --------------------------------------------------------------------------------------
 
@@ -468,16 +584,24 @@ def test_dual_gradient_matches_central_fd(oracle):
         fd = (oracle.track_loss(BLUEROV2, x0, ap, 1, 0.01, pref, qref, mult=mult)
               - oracle.track_loss(BLUEROV2, x0, am, 1, 0.01, pref, qref, mult=mult)) / (2 * h)
         np.testing.assert_allclose(g_act[t, i], fd, rtol=1e-6, atol=1e-8)
-    # hydrodynamic parameters, absolute units: perturb the multiplier by h / nominal
+    # hydrodynamic parameters, absolute units.  The five-point stencil
+    # (f(-2s) - 8 f(-s) + 8 f(s) - f(2s)) / 12s with a step of 3e-3 of each env's own
+    # parameter value has truncation error O(s^4) and rounding error ~ eps L / s, both
+    # far below the tolerance: the worst env and parameter sits at 0.0074 of it (a
+    # central difference with a step of 1e-6 sat at 0.87, on its rounding floor).
     nominal = np.concatenate([BLUEROV2["added_mass"], BLUEROV2["d_lin"], BLUEROV2["d_quad"],
                               [BLUEROV2["buoyancy"]]])
+    m64 = mult.astype(np.float64)
     for j in range(19):
-        mp, mm = mult.astype(np.float64).copy(), mult.astype(np.float64).copy()
-        step = h * max(1.0, nominal[j] * mult[4 + j].max())
-        mp[4 + j] += step / nominal[j]
-        mm[4 + j] -= step / nominal[j]
-        fd = (oracle.track_loss(BLUEROV2, x0, act, 1, 0.01, pref, qref, mult=mp)
-              - oracle.track_loss(BLUEROV2, x0, act, 1, 0.01, pref, qref, mult=mm)) / (2 * step)
+        p = nominal[j] * m64[4 + j]                  # absolute parameter, per env
+        step = 3e-3 * p
+
+        def loss_at(k):
+            m = m64.copy()
+            m[4 + j] = (p + k * step) / nominal[j]
+            return oracle.track_loss(BLUEROV2, x0, act, 1, 0.01, pref, qref, mult=m)
+
+        fd = (loss_at(-2) - 8 * loss_at(-1) + 8 * loss_at(1) - loss_at(2)) / (12 * step)
         np.testing.assert_allclose(g_th[j], fd, rtol=2e-6, atol=1e-9)
     # initial state
     for i in [0, 4, 9, 12]:

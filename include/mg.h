@@ -111,12 +111,21 @@ const char* mg_status_str(mg_status s);
  * sim is NULL.  Valid until the next call on the same sim. */
 const char* mg_last_error(const mg_sim* sim);
 
-/* Allocates the device buffers (state, parameters, derived constants) and
- * leaves every env at rest at the origin with nominal parameters (as
- * mg_reset with NULL state and multipliers).  Synchronous. */
+/* The parallel environment instances of Sec. I (second contribution) and
+ * Sec. II (component 1: BlueROV2 / BlueROV2 Heavy dynamics): allocates the
+ * device buffers (state, parameters, derived constants) and leaves every env
+ * at rest at the origin with nominal parameters (as mg_reset with NULL state
+ * and multipliers).  Synchronous.  MG_ERR_INVALID for a malformed config,
+ * MG_ERR_UNSUPPORTED for a class the GPU path does not implement, MG_ERR_OOM
+ * if the buffers cannot be had; *out is NULL on any error. */
 mg_status mg_create(const mg_config* cfg, mg_sim** out);
-/* Waits for the sim's stream and frees everything; NULL is ignored. */
+/* Ends the environment instances mg_create made (Sec. II, component 1):
+ * waits for the sim's stream and frees everything the sim owns, never the
+ * caller's buffers; NULL is ignored. */
 void mg_destroy(mg_sim* sim);
+/* The hipStream_t (or NULL: the default stream) every later call of this sim
+ * is enqueued on, so that stepping orders itself with the learner's work on
+ * the same GPU (Sec. III); NULL sim: MG_ERR_INVALID. */
 mg_status mg_set_stream(mg_sim* sim, void* stream);
 int32_t mg_state_dim(const mg_sim* sim);      /* D, or -1 for NULL */
 int32_t mg_action_dim(const mg_sim* sim);     /* N_max = largest n_thr, or -1 */
@@ -135,10 +144,15 @@ int64_t mg_num_envs(const mg_sim* sim);       /* E, or -1 */
  *               non-finite after its next step. */
 mg_status mg_reset(mg_sim* sim, const int64_t* env_ids, int64_t n_ids, const float* state,
                    const float* param_mult);
-/* Absolute parameters for all envs, device [23][E] (same order as the
- * multipliers), refactoring M as mg_reset does.  State is untouched. */
+/* Physical-parameter domain randomisation given as absolute values (Sec. II,
+ * component 1): device [23][E] (same order as the multipliers), refactoring
+ * M = M_RB + M_A of Eq. (1) as mg_reset does.  State is untouched.  Errors as
+ * mg_reset (NULL params: MG_ERR_INVALID). */
 mg_status mg_set_params(mg_sim* sim, const float* params);
-/* Overwrites every env's state from device [D][E]; parameters are kept. */
+/* Sets the pose eta and body velocity nu of Eq. (1) (Sec. II; as the
+ * quaternion state described above) and the thruster states of every env
+ * from device [D][E]; parameters are kept.  Together with mg_get_state this
+ * is a bitwise-exact save and resume.  NULL state: MG_ERR_INVALID. */
 mg_status mg_set_state(mg_sim* sim, const float* state);
 
 /* Advances every env by n_ctrl control steps in ONE fused launch per class:
@@ -155,26 +169,35 @@ mg_status mg_set_state(mg_sim* sim, const float* state);
  *            two-pass reduction).  Or NULL. */
 mg_status mg_step(mg_sim* sim, const float* actions, int32_t n_ctrl, const float* targets,
                   float* traj, double* stats);
-/* The same discrete map as mg_step, computed by the plain kernel: one launch
+/* The sub-simulation steps of Sec. II (the paragraph after Eq. (1)) taken one
+ * per launch, as an engine that updates the dynamics once per sub-step does:
+ * the same discrete map as mg_step, computed by the plain kernel, one launch
  * per RK4 sub-step per class, state round-tripping HBM between launches.  The
  * thruster lag states advance by the one-sub-step lag factor per launch
  * instead of its S-th power once per control step, so results agree with
  * mg_step to rounding, not bitwise. */
 mg_status mg_step_plain(mg_sim* sim, const float* actions, int32_t n_ctrl, const float* targets,
                         float* traj, double* stats);
-/* T control steps as T launches per class (plain != 0: T * substeps
+/* A sequence of T Gym-style steps (Sec. III) of every env with its
+ * throttles (Eq. (3)) given up front, each of `substeps` sub-steps (Sec. II):
+ * T control steps as T launches per class (plain != 0: T * substeps
  * launches), replayed from a HIP graph that is captured on first use and
  * cached for this exact argument tuple (at most 64 tuples per sim; the 65th
  * empties the cache, after waiting for the sim's stream).  Arguments as
  * mg_step with n_ctrl = T. */
 mg_status mg_rollout(mg_sim* sim, const float* actions, int32_t T, const float* targets,
                      float* traj, double* stats, int32_t plain);
-/* Copies the state [D][E] to out.  out_on_device != 0: device pointer,
- * enqueued; 0: host pointer, synchronous (waits for the stream). */
+/* Reads back eta and nu of Eq. (1) (Sec. II) with the thruster states: copies
+ * the state [D][E], caller env order, to out.  out_on_device != 0: device
+ * pointer, enqueued; 0: host pointer, synchronous (waits for the stream).
+ * NULL out: MG_ERR_INVALID. */
 mg_status mg_get_state(mg_sim* sim, float* out, int32_t out_on_device);
-/* Copies the absolute parameters [23][E], same rules as mg_get_state. */
+/* Reads back the randomised physical parameters (Sec. II, component 1):
+ * copies the absolute parameters [23][E], same rules as mg_get_state. */
 mg_status mg_get_params(mg_sim* sim, float* out, int32_t out_on_device);
-/* Waits for the sim's stream; returns MG_ERR_DEVICE if queued work failed. */
+/* Simulation and learner share one GPU with few host transfers (Sec. III), so
+ * every call above is stream-ordered; this is the host's wait: it blocks until
+ * the sim's stream is idle and returns MG_ERR_DEVICE if queued work failed. */
 mg_status mg_synchronize(mg_sim* sim);
 
 /* The split integration that Sec. II describes, as a variant of mg_step: a

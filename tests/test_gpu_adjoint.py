@@ -307,3 +307,36 @@ def test_full_size_adjoint_sampled(mgmod, oracle):
         assert _rel(g_act[:, :, k], r_act[:, :, k]) <= TOL_GRAD
         assert _rel(g_th[:, k], r_th[:, k]) <= TOL_GRAD
         assert _rel(g_x0[:, k], r_x0[:, k]) <= TOL_GRAD
+
+
+@pytest.mark.parametrize("lag", [True, False])
+def test_single_segment_one_wave_backward(mgmod, oracle, lag):
+    """The backward that recomputes its one segment itself on a launch of at most one wave
+    per SIMD (T <= ckpt_every, few envs): 8 thrusters with and without lag, 1500 envs, 6
+    control steps of 3 sub-steps, checkpoint every 8.  Its gradients equal, bitwise, those of
+    the same envs with checkpoints every 3 (whole-rollout recomputation, then the sweep), and
+    match the oracle's dual-number gradient on 9 envs including the ragged tail."""
+    v = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05 if lag else 0.0)
+    D = 21 if lag else 13
+    E, T, S, dt = 1500, 6, 3, 0.005
+    x0 = initial_state(E, D, 381)
+    if lag:
+        x0[13:] = np.random.default_rng(382).uniform(-20, 20, size=(8, E)).astype(np.float32)
+    act = actions(T, 8, E, 383) * np.float32(1.1)
+    mult = param_multipliers(E, 0.2, 384)
+    pref, qref = circle_waypoints(T, E, 0.015, 385)
+    say(f"adjoint one segment, one wave: N=8 lag={lag} E={E} T={T} K=8")
+    _, g_act, g_th, g_x0, _ = _gpu_grads(mgmod, v, x0, act, mult, pref, qref, S, dt, 8)
+    say(f"adjoint whole-rollout recompute: N=8 lag={lag} E={E} T={T} K=3")
+    _, w_act, w_th, w_x0, _ = _gpu_grads(mgmod, v, x0, act, mult, pref, qref, S, dt, 3)
+    np.testing.assert_array_equal(g_act, w_act)
+    np.testing.assert_array_equal(g_th, w_th)
+    np.testing.assert_array_equal(g_x0, w_x0)
+    sub = np.r_[0:1500:211, 1498, 1499]
+    _, r_act, r_th, r_x0 = oracle.track_loss_grad(
+        v, x0[:, sub], act[:, :, sub], S, dt, pref[:, :, sub], qref[:, :, sub],
+        mult=mult[:, sub], want_x0=True)
+    for k, e in enumerate(sub):
+        assert _rel(g_act[:, :, e], r_act[:, :, k]) <= TOL_GRAD
+        assert _rel(g_th[:, e], r_th[:, k]) <= TOL_GRAD
+        assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD

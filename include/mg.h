@@ -42,6 +42,7 @@
 #ifndef MG_H
 #define MG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -315,6 +316,26 @@ mg_status mg_adj_forward(mg_sim* sim, const float* actions, int32_t T, int32_t c
 mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, int32_t T,
                           int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
                           float* dL_dtheta, float* dL_dx0);
+
+/* mg_adj_backward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (bitwise) as
+ * mg_adj_backward, but the sub-step states it recomputes go to a static
+ * scratch array of MG_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends; the call itself allocates
+ * nothing.  The whole rollout's states are used when there is more than one
+ * segment and T * substeps * D * E_pad floats fit (E_pad: the env count padded
+ * per class to 256), else one segment's, ckpt_every * substeps * D * E_pad
+ * floats (min(T, ckpt_every) for T < ckpt_every); a segment beyond the scratch
+ * returns MG_ERR_INVALID with nothing done.  The scratch is shared by every
+ * sim on the device and keeps the last call's contents (every float read is
+ * first written by the same call): calls that overlap on one device, from any
+ * sim or stream, race and must be ordered by the caller.  MG_ERR_DEVICE if the
+ * scratch was not set up (mg_create looks it up once per device). */
+#define MG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mg_status mg_adj_backward_noalloc(mg_sim* sim, const float* ckpt, const float* actions,
+                                  int32_t T, int32_t ckpt_every, const float* dL_dtraj,
+                                  float* dL_dact, float* dL_dtheta, float* dL_dx0);
 
 /* ---- serving loop -------------------------------------------------------------------
  * Serves step and rollout requests of uneven env counts from many client

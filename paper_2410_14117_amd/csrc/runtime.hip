@@ -9,15 +9,44 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
 
 using namespace mg;
 
+// Recomputation scratch of mg_adj_backward_noalloc: one copy per device,
+// allocated when the library's device code is loaded and held until the
+// process ends.  Host code never uses this name as an address (on the host it
+// is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns, kept per device in g_noalloc_ptr.
+static __device__ __align__(256) float scratch[MG_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+float* g_noalloc_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device with
+// that device current (the caller's DeviceGuard makes it so); NULL if the
+// lookup fails or the ordinal is beyond kMaxDevices.
+float* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_noalloc_ptr[device] = static_cast<float*>(p);
+  }
+  return g_noalloc_ptr[device];
+}
 
 constexpr size_t kMaxCachedGraphs = 64;   // rollout graphs kept per sim
 
@@ -363,6 +392,30 @@ AdjArgs adj_args(mg_sim* s, const float* actions, int32_t T, int32_t K) {
   return a;
 }
 
+// The backward's launches: per class, the whole rollout's recomputation into
+// buf (whole) and the reverse sweep, or the sweep that recomputes each segment
+// into buf itself.  Allocates nothing.
+mg_status adj_backward_launch(mg_sim* s, const float* ckpt, const float* actions, int32_t T,
+                              int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
+                              float* dL_dtheta, float* dL_dx0, float* buf, bool whole) {
+  AdjArgs a = adj_args(s, actions, T, ckpt_every);
+  a.ckpt = const_cast<float*>(ckpt);
+  a.gtraj = dL_dtraj;
+  a.gact = dL_dact;
+  a.gtheta = dL_dtheta;
+  a.gx0 = dL_dx0;
+  a.segbuf = buf;
+  a.recomputed = whole ? 1 : 0;
+  for (int k = 0; k < s->n_classes; ++k) {
+    a.seg_start = s->seg_start[k];
+    a.seg_len = s->seg_len[k];
+    a.zb = (float)s->nominal[k].zb;
+    if (whole) MG_HIP(s, launch_adj_recompute(s->cc[k], a, s->stream));
+    MG_HIP(s, launch_adjoint(true, s->cc[k], a, s->stream));
+  }
+  return MG_OK;
+}
+
 // internal [rows][Ep] <- caller [rows][E] (device)
 mg_status copy_in(mg_sim* s, const float* src, int32_t rows, float* dst) {
   if (!s->perm) {
@@ -581,6 +634,10 @@ mg_status mg_create(const mg_config* cfg, mg_sim** out) {
     (void)hipGetLastError();
     return bail(MG_ERR_DEVICE, "initial reset failed: " + s->err);
   }
+  // set-up of mg_adj_backward_noalloc: the device address of its static
+  // scratch, looked up once per device while that device is current
+  if (!noalloc_scratch(s->device))
+    return bail(MG_ERR_DEVICE, "cannot look up the static adjoint scratch on this device");
   *out = s;
   return MG_OK;
 }
@@ -902,22 +959,35 @@ mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* actions, in
     }
     s->segbuf_cap = seg_floats;
   }
-  AdjArgs a = adj_args(s, actions, T, ckpt_every);
-  a.ckpt = const_cast<float*>(ckpt);
-  a.gtraj = dL_dtraj;
-  a.gact = dL_dact;
-  a.gtheta = dL_dtheta;
-  a.gx0 = dL_dx0;
-  a.segbuf = s->segbuf;
-  a.recomputed = whole ? 1 : 0;
-  for (int k = 0; k < s->n_classes; ++k) {
-    a.seg_start = s->seg_start[k];
-    a.seg_len = s->seg_len[k];
-    a.zb = (float)s->nominal[k].zb;
-    if (whole) MG_HIP(s, launch_adj_recompute(s->cc[k], a, s->stream));
-    MG_HIP(s, launch_adjoint(true, s->cc[k], a, s->stream));
-  }
-  return MG_OK;
+  return adj_backward_launch(s, ckpt, actions, T, ckpt_every, dL_dtraj, dL_dact, dL_dtheta,
+                             dL_dx0, s->segbuf, whole);
+}
+
+mg_status mg_adj_backward_noalloc(mg_sim* s, const float* ckpt, const float* actions, int32_t T,
+                                  int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
+                                  float* dL_dtheta, float* dL_dx0) {
+  mg_status st = adj_common(s, actions, T, ckpt_every, ckpt);
+  if (st) return st;
+  if (!dL_dtraj || !dL_dact || !dL_dtheta)
+    return fail(s, MG_ERR_INVALID, "dL_dtraj, dL_dact and dL_dtheta must not be NULL");
+  // the same choice as mg_adj_backward, bounded by the static scratch instead
+  // of by what can be allocated
+  const size_t cap = MG_NOALLOC_SCRATCH_BYTES / sizeof(float);
+  const int32_t nseg = (T + ckpt_every - 1) / ckpt_every;
+  const size_t whole_floats = (size_t)T * s->substeps * s->D * (size_t)s->Ep;
+  const size_t seg_floats = (size_t)std::min(ckpt_every, T) * s->substeps * s->D * (size_t)s->Ep;
+  const bool whole = nseg > 1 && nseg <= 65535 && whole_floats <= cap;
+  if (!whole && seg_floats > cap)
+    return fail(s, MG_ERR_INVALID,
+                "mg_adj_backward_noalloc: one segment's sub-step states (" +
+                    std::to_string(seg_floats * sizeof(float)) + " bytes) exceed the " +
+                    std::to_string((size_t)MG_NOALLOC_SCRATCH_BYTES) +
+                    "-byte static scratch; use a smaller ckpt_every or mg_adj_backward");
+  DeviceGuard g(s->device);
+  float* buf = g_noalloc_ptr[s->device];   // set by mg_create on this device
+  if (!buf) return fail(s, MG_ERR_DEVICE, "static adjoint scratch not set up on this device");
+  return adj_backward_launch(s, ckpt, actions, T, ckpt_every, dL_dtraj, dL_dact, dL_dtheta,
+                             dL_dx0, buf, whole);
 }
 
 mg_status mg_synchronize(mg_sim* s) {

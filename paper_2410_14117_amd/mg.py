@@ -143,6 +143,8 @@ _SIGS = {
     "mg_adj_forward": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
     "mg_adj_backward": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                          _vp, _vp]),
+    "mg_adj_backward_noalloc": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                                 _vp, _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -423,22 +425,31 @@ class Sim:
         self._check(lib().mg_adj_forward(self._h, a, T, K, ck, tr))
         return ckpt, traj
 
-    def adj_backward(self, ckpt, actions, ckpt_every, dL_dtraj, want_x0=True):
-        """Returns (dL/d actions [T][N_max][E], dL/d theta [19][E], dL/d x0 [D][E] or None)."""
+    def adj_backward(self, ckpt, actions, ckpt_every, dL_dtraj, want_x0=True, out=None,
+                     noalloc=False):
+        """Returns (dL/d actions [T][N_max][E], dL/d theta [19][E], dL/d x0 [D][E] or None).
+        out: optional (dL_dact, dL_dtheta, dL_dx0 or None) tensors to write into;
+        noalloc: call mg_adj_backward_noalloc (static scratch, no device allocation)."""
         import torch
         T, E, D, N = int(actions.shape[0]), self.n_envs, self.state_dim, self.action_dim
         K = int(ckpt_every)
         nseg = (T + K - 1) // K
         dev = f"cuda:{self.device}"
-        gact = torch.empty((T, N, E), dtype=torch.float32, device=dev)
-        gth = torch.empty((NUM_THETA, E), dtype=torch.float32, device=dev)
-        gx0 = torch.empty((D, E), dtype=torch.float32, device=dev) if want_x0 else None
+        if out is None:
+            gact = torch.empty((T, N, E), dtype=torch.float32, device=dev)
+            gth = torch.empty((NUM_THETA, E), dtype=torch.float32, device=dev)
+            gx0 = torch.empty((D, E), dtype=torch.float32, device=dev) if want_x0 else None
+        else:
+            gact, gth, gx0 = out
+        ga = _ptr(gact, torch.float32, (T, N, E), "dL_dact")
+        gt = _ptr(gth, torch.float32, (NUM_THETA, E), "dL_dtheta")
+        gx = _ptr(gx0, torch.float32, (D, E), "dL_dx0")
         ck = _ptr(ckpt, torch.float32, (nseg, D, E), "ckpt")
         a = _ptr(actions, torch.float32, (T, N, E), "actions")
         g = _ptr(dL_dtraj, torch.float32, (T, D, E), "dL_dtraj")
         self._bind_stream()
-        self._check(lib().mg_adj_backward(self._h, ck, a, T, K, g, gact.data_ptr(), gth.data_ptr(),
-                                          None if gx0 is None else gx0.data_ptr()))
+        fn = lib().mg_adj_backward_noalloc if noalloc else lib().mg_adj_backward
+        self._check(fn(self._h, ck, a, T, K, g, ga, gt, gx))
         return gact, gth, gx0
 
 

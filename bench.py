@@ -29,10 +29,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "env-steps/s of batched Fossen RK4 step at 1M envs; served p50/p99 latency"
 PEAK_FP32_VALU = 157.3e12      # MI355X published FP32 vector peak (packed)
-# one FP32 FMA per lane per clock without packed math or dual issue:
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
-PEAK_FP32_SINGLE_ISSUE = 78.6e12
 PEAK_HBM = 8.0e12
+# Algorithmic work of one env-substep for the roofline: the flops a structured
+# formulation of the RK4 step needs (four right-hand sides of ~250-280 flops,
+# the RK4 combination ~280, the renormalisation ~15; FMA = 2), ~1.35 kflop, and
+# the bytes the plain per-sub-step kernel must move (state in and out, one
+# throttle frame, the 23 randomised parameters).
+ALGO_FLOPS_PER_ENV_SUBSTEP = 1350.0
 
 
 def substep_flops(n_thr, lag, substeps):
@@ -63,6 +66,13 @@ def split_substep_flops(n_thr, lag, substeps):
     over the sub-steps."""
     core = 14 + 83 + 12 + 14 + 12 + 36 + 28 + 12
     return core + (16 * n_thr if lag else 0) + (14 * n_thr - 6) / substeps
+
+
+def fused_algo_bytes(n_thr, lag):
+    """Algorithmic HBM bytes of one env in one fused launch (one control step of S
+    sub-steps): state read once and written once, one throttle frame, the 23 randomised
+    parameters -- the plain kernel's per-sub-step bytes, moved once per control step."""
+    return plain_bytes(n_thr, lag)
 
 
 def plain_bytes(n_thr, lag):
@@ -142,7 +152,62 @@ def cpu_baseline(n_envs=1 << 16, n_ctrl=200, n_envs_1t=1024):
                       f"{threads} threads",
             "value_1_thread": n_envs_1t * n_ctrl * c.substeps / dt1,
             "sample_1_thread": f"{n_envs_1t} of those envs (half of each class), same steps, "
-                               f"one thread; {dt1:.2f} s"}
+                               f"one thread; {dt1:.2f} s",
+            "other_workloads": cpu_other_workloads(threads)}
+
+
+def cpu_other_workloads(threads):
+    """The oracle on the other workloads, in full where that takes seconds: 64 BlueROV2
+    envs x 1000 steps (nominal, linear map); 4096 Heavy envs x 1000 control steps x 4
+    sub-steps (+-20 %, quadratic map, lag); the 8192-env, 64-step tracking-loss forward;
+    and its dual-number gradient (throttles, 19 parameters, x0) on 16 envs."""
+    from oracle import oracle
+    from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
+                           actions, param_multipliers, circle_waypoints)
+    out = {}
+    c1 = CONFIGS["c1"]
+    x0 = initial_state(c1.n_envs, 13, c1.seed_base + 2)
+    act = actions(c1.n_ctrl, 6, c1.n_envs, c1.seed_base + 3)
+    t0 = time.perf_counter()
+    oracle.rollout(BLUEROV2, x0, act, c1.substeps, c1.dt_sub, want_stats=True, nthreads=threads)
+    dt = time.perf_counter() - t0
+    out["c1_full"] = {"env_steps_per_s": c1.n_envs * c1.n_ctrl * c1.substeps / dt, "s": dt,
+                      "workload": "64 BlueROV2 envs x 1000 steps of 10 ms, nominal, linear map"}
+    c2 = CONFIGS["c2"]
+    heavy = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)
+    x0 = initial_state(c2.n_envs, 21, c2.seed_base + 2)
+    act = actions(c2.n_ctrl, 8, c2.n_envs, c2.seed_base + 3)
+    mult = param_multipliers(c2.n_envs, c2.rho, c2.seed_base + 1)
+    t0 = time.perf_counter()
+    oracle.rollout(heavy, x0, act, c2.substeps, c2.dt_sub, mult=mult, want_stats=True,
+                   nthreads=threads)
+    dt = time.perf_counter() - t0
+    out["c2_full"] = {"env_steps_per_s": c2.n_envs * c2.n_ctrl * c2.substeps / dt, "s": dt,
+                      "workload": "4096 Heavy envs x 1000 control steps x 4 sub-steps of 5 ms, "
+                                  "+-20 %, quadratic map, 0.05 s lag"}
+    c4 = CONFIGS["c4"]
+    E, T = c4.n_envs, c4.n_ctrl
+    x0 = initial_state(E, 13, c4.seed_base + 2)
+    act = actions(T, 6, E, c4.seed_base + 3)
+    pref, qref = circle_waypoints(T, E, c4.dt_sub, c4.seed_base + 4, omega=c4.extra["omega"])
+    t0 = time.perf_counter()
+    oracle.track_loss(BLUEROV2, x0, act, c4.substeps, c4.dt_sub, pref, qref, nthreads=threads)
+    dt_f = time.perf_counter() - t0
+    sub = slice(0, 16)
+    t0 = time.perf_counter()
+    oracle.track_loss_grad(BLUEROV2, np.ascontiguousarray(x0[:, sub]),
+                           np.ascontiguousarray(act[:, :, sub]), c4.substeps, c4.dt_sub,
+                           np.ascontiguousarray(pref[:, :, sub]),
+                           np.ascontiguousarray(qref[:, :, sub]), want_x0=True, nthreads=threads)
+    dt_g = time.perf_counter() - t0
+    out["c4_forward"] = {"ms": dt_f * 1e3, "env_steps_per_s": E * T / dt_f,
+                         "workload": "8192 BlueROV2 envs x 64 steps of 10 ms with the tracking "
+                                     "loss"}
+    out["c4_dual_gradient_16_envs"] = {
+        "ms": dt_g * 1e3, "gradients_per_s": 16 / dt_g,
+        "workload": "forward-mode (dual number) gradient of the tracking loss w.r.t. 64 x 6 "
+                    "throttles, 19 parameters and x0, envs 0-15"}
+    return out
 
 
 def bench_adjoint(torch, mg, reps=5, n_envs=None):
@@ -674,7 +739,11 @@ def main():
     torch.cuda.synchronize()
     fused_ms = ev0.elapsed_time(ev1) / reps
     flops_rollout = (n_b * substep_flops(6, True, S) + n_h * substep_flops(8, True, S)) * T * S
-    achieved = flops_rollout / (fused_ms * 1e-3)
+    executed = flops_rollout / (fused_ms * 1e-3)
+    algo_flops_rollout = ALGO_FLOPS_PER_ENV_SUBSTEP * E * S * T
+    achieved = algo_flops_rollout / (fused_ms * 1e-3)
+    traffic = load_traffic("k_step_fused_control_step")
+    algo_bytes_ctrl = n_b * fused_algo_bytes(6, True) + n_h * fused_algo_bytes(8, True)
     st = stats.cpu().numpy()
 
     out = {
@@ -691,15 +760,23 @@ def main():
         "sim_seconds_per_wall_second": value * c.dt_sub,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
-                     "peak_single_issue": PEAK_FP32_SINGLE_ISSUE / 1e12,
-                     "frac_single_issue": achieved / PEAK_FP32_SINGLE_ISSUE,
-                     "traffic": load_traffic("k_step_fused_control_step"),
+                     "traffic": traffic,
                      "kernel": "k_step<6|8,lag> fused: the BlueROV2 and Heavy launches of one "
                                "control step (16 RK4 sub-steps each), run concurrently",
                      "control_step_us": fused_ms * 1e3 / T,
-                     "flops_per_control_step": flops_rollout / T,
-                     "flops_per_env_substep": {"bluerov2": substep_flops(6, True, S),
-                                               "heavy": substep_flops(8, True, S)}},
+                     "counted": f"algorithmic: {ALGO_FLOPS_PER_ENV_SUBSTEP:.0f} flop per "
+                                "env-substep (structured RK4 step) x env-substeps per launch",
+                     "algorithmic_flops_per_control_step": algo_flops_rollout / T,
+                     "executed": {"achieved": executed / 1e12,
+                                  "frac": executed / PEAK_FP32_VALU,
+                                  "flops_per_control_step": flops_rollout / T,
+                                  "flops_per_env_substep": {
+                                      "bluerov2": substep_flops(6, True, S),
+                                      "heavy": substep_flops(8, True, S)},
+                                  "counted": "the kernel's own formulation, instruction by "
+                                             "instruction (SQ_INSTS_VALU_FLOPS_FP32 agrees)"},
+                     "algorithmic_bytes_per_control_step": algo_bytes_ctrl,
+                     "traffic_ratio": None if traffic is None else traffic / algo_bytes_ctrl},
         "stats_last_step": {"mean_dist": st[-1, 0] / max(1, E - st[-1, 3]),
                             "max_dist": st[-1, 1], "nonfinite": st[-1, 3]},
     }

@@ -68,6 +68,11 @@ def split_substep_flops(n_thr, lag, substeps):
     return core + (16 * n_thr if lag else 0) + (14 * n_thr - 6) / substeps
 
 
+def progress(msg):
+    """One line on stderr as each stage of the run ends (the JSON line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def fused_algo_bytes(n_thr, lag):
     """Algorithmic HBM bytes of one env in one fused launch (one control step of S
     sub-steps): state read once and written once, one throttle frame, the 23 randomised
@@ -261,19 +266,20 @@ def bench_adjoint(torch, mg, reps=5, n_envs=None):
             "gradients_per_s": E / ((t_fwd + t_bwd) * 1e-3)}
 
 
-def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup_s=0.5,
+def bench_serving(torch, mg, duration_s=30.0, fifo_plain=False, seed=5005, warmup_s=5.0,
                   reserve_bytes=2 << 30, steps_per_tick=1):
     """C5: 32 clients with Poisson arrivals (2000 req/s aggregate), env counts log-uniform in
     [16, 65536], half step requests (1 control step) and half rollouts (1..64 steps), mixed
     BlueROV2 / Heavy (+-20 % randomisation, 4 RK4 sub-steps of 5 ms per control step),
-    inputs resident on the device; latency = arrival -> final states in host memory.  The
-    server creates `reserve_bytes` of page memory at start, and a warm-up trace of
-    `warmup_s` (another seed) runs first on it, so that the timed trace finds its pages and
-    staging buffers allocated.  `steps_per_tick`: most control steps a request advances
-    per tick."""
-    import threading
+    initial states and multipliers resident on the device, throttles generated on the
+    device from a per-request seed; latency = arrival -> final states in host memory.  The
+    trace is replayed by 32 native client threads (one per client, libmg_clients.so), each
+    submitting its own requests at their arrival times and waiting for them.  The server
+    creates `reserve_bytes` of page memory at start, and a warm-up trace of `warmup_s`
+    (another seed) runs first on it, so that the timed trace finds its pages and staging
+    buffers allocated.  `steps_per_tick`: most control steps a request advances per tick."""
     from workloads import (BLUEROV2, BLUEROV2_HEAVY, CONFIGS, vehicle_variant, initial_state,
-                           actions, param_multipliers, env_classes)
+                           param_multipliers, env_classes)
     c = CONFIGS["c5"]
     classes = [vehicle_variant(BLUEROV2, thr_map=1, thr_tau=0.05),
                vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05)]
@@ -284,15 +290,13 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
     x0[19:, cls == 0] = 0
     x0_d = torch.from_numpy(x0).to(dev)
     mult_d = torch.from_numpy(param_multipliers(P, c.rho, c.seed_base + 1)).to(dev)
-    act_d = torch.from_numpy(actions(LMAX, 8, P, c.seed_base + 3)).to(dev)
     torch.cuda.synchronize()
     srv = mg.Server(classes, c.dt_sub, c.substeps, fifo_plain=fifo_plain,
                     reserve_bytes=reserve_bytes, steps_per_tick=steps_per_tick)
     n_clients, rate = c.extra["clients"], c.extra["rate"]
 
     def make_trace(seconds, trace_seed):
-        # per client a Poisson stream of rate / n_clients; the 32 streams merged into one
-        # arrival sequence
+        # per client a Poisson stream of rate / n_clients
         rng = np.random.Generator(np.random.PCG64(trace_seed))
         trace = []
         for k in range(n_clients):
@@ -305,61 +309,44 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
                                                  np.log(c.extra["env_hi"])))))
                 L = 1 if rng.random() < 0.5 else int(rng.integers(1, LMAX + 1))
                 off = int(rng.integers(0, P - n + 1))
-                trace.append((k, t, n, L, off))
+                trace.append((k, t, n, L, off, int(rng.integers(0, 2 ** 63))))
         trace.sort(key=lambda r: r[1])
         return trace
 
     def run(trace):
-        # one thread submits at the scheduled times (open loop: latency counts from the
-        # scheduled arrival); then every request is waited for.  The clients' result
+        # open loop: latency counts from the scheduled arrival.  The clients' result
         # buffers are allocated and touched before the trace starts, as a serving client
         # keeps them (fresh memory would add its page faults to the measured latency).
-        results, lags = [], []
-        sizes = [D * n for _, _, n, _, _ in trace]
+        sizes = [D * r[2] for r in trace]
         arena = np.ones(sum(sizes), np.float32)
         starts = np.concatenate([[0], np.cumsum(sizes)])
-        outs = [arena[starts[i]:starts[i + 1]].reshape(D, -1) for i in range(len(trace))]
+        reqs = [{"client": k, "at_ns": int(t * 1e9), "n_envs": n, "n_steps": L,
+                 "x0_ptr": x0_d.data_ptr() + 4 * off, "ld": P,
+                 "out": arena[starts[i]:starts[i + 1]].reshape(D, -1),
+                 "env_class": cls[off:off + n], "mult_ptr": mult_d.data_ptr() + 4 * off,
+                 "action_seed": aseed}
+                for i, (k, t, n, L, off, aseed) in enumerate(trace)]
         t0 = mg.Server.clock_ns() + 50_000_000
-
-        def submitter():
-            for i, (_, t, n, L, off) in enumerate(trace):
-                at = t0 + int(t * 1e9)
-                while True:
-                    wait_ns = at - mg.Server.clock_ns()
-                    if wait_ns <= 0:
-                        break
-                    if wait_ns > 300_000:
-                        time.sleep((wait_ns - 200_000) * 1e-9)
-                lags.append(mg.Server.clock_ns() - at)
-                st, tk = srv.submit(n, L, x0_d.data_ptr() + 4 * off, act_d.data_ptr() + 4 * off,
-                                    P, outs[i], env_class=cls[off:off + n],
-                                    mult_ptr=mult_d.data_ptr() + 4 * off, arrival_ns=at)
-                results.append((st, tk, n, L))
-
-        th = threading.Thread(target=submitter)
         w0 = time.perf_counter()
-        th.start()
-        th.join()
-        lats, env_steps = [], 0
-        for st, tk, n, L in results:
-            if st != 0:
-                continue
-            st2, lat = srv.wait(tk, 600_000_000)
-            if st2 == 0:
-                lats.append(lat)
-                env_steps += n * L
-        return np.array(lats), env_steps, time.perf_counter() - w0, lags
+        status, lat, lag = srv.replay(reqs, t0, n_clients)
+        wall = time.perf_counter() - w0 - 0.05
+        ok = status == 0
+        env_steps = sum(r[2] * r[3] for r, o in zip(trace, ok) if o)
+        return lat[ok], env_steps, wall, lag, int((~ok).sum())
 
     if warmup_s > 0:
         run(make_trace(warmup_s, seed + 1))
     s0 = srv.stats()
     trace = make_trace(duration_s, seed)
-    lats, env_steps, wall, lags = run(trace)
+    lats, env_steps, wall, lags, failed = run(trace)
     s1 = srv.stats()
     srv.close()
     ticks = max(1, s1["ticks"] - s0["ticks"])
     return {"mode": "fifo_plain_one_at_a_time" if fifo_plain else "continuous_batching",
-            "requests": len(trace), "completed": int(len(lats)),
+            "clients": f"{n_clients} native client threads, each submitting its own Poisson "
+                       "stream and waiting for its tickets",
+            "actions": "generated on the device from a per-request SplitMix64 seed",
+            "requests": len(trace), "completed": int(len(lats)), "failed": failed,
             "offered_req_per_s": len(trace) / duration_s, "trace_s": duration_s,
             "warmup_trace_s": warmup_s, "reserved_bytes": reserve_bytes,
             "steps_per_tick": steps_per_tick,
@@ -369,6 +356,7 @@ def bench_serving(torch, mg, duration_s=2.0, fifo_plain=False, seed=5005, warmup
             "p50_ms": float(np.percentile(lats, 50) * 1e3),
             "p99_ms": float(np.percentile(lats, 99) * 1e3),
             "p999_ms": float(np.percentile(lats, 99.9) * 1e3),
+            "max_ms": float(lats.max() * 1e3),
             "max_active_envs": s1["max_active_envs"], "ticks": ticks,
             "host_issue_us_per_tick": (s1["issue_ns"] - s0["issue_ns"]) / ticks / 1e3,
             "host_blocked_us_per_tick": (s1["wait_ns"] - s0["wait_ns"]) / ticks / 1e3,
@@ -659,7 +647,11 @@ def main():
     ap.add_argument("--no-task", action="store_true")
     ap.add_argument("--no-policy", action="store_true")
     ap.add_argument("--no-split", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="timed serving trace (after a --serve-warmup trace of another seed)")
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-aux-seconds", type=float, default=5.0,
+                    help="timed trace of the one-step-per-tick comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one device copy of 1 GiB (read 1 GiB, write 1 GiB) whose "
                          "FETCH_SIZE / WRITE_SIZE calibrate the counters of a --pmc run")
@@ -781,6 +773,7 @@ def main():
                             "max_dist": st[-1, 1], "nonfinite": st[-1, 3]},
     }
 
+    progress(f"fused rollout timed: {ms_step:.2f} ms per step")
     if not args.no_plain:
         sim.reset(state=x0, param_mult=mult)
         sim.rollout(act, stats=stats, plain=True)     # capture
@@ -812,10 +805,13 @@ def main():
             "env_steps_per_s": env_substeps / (eager_ms * 1e-3), "ms_per_rollout": eager_ms,
             "avg_launch_us": eager_ms * 1e3 / (2 * T * S),
             "frac_hbm": bytes_rollout / (eager_ms * 1e-3) / PEAK_HBM}
+        progress("plain comparator timed")
     if not args.no_task:
         out["task_epilogue"] = bench_task(torch, sim, act, x0, n_b, n_h)
+        progress("task epilogue timed")
     if not args.no_split:
         out["split_scheme"] = bench_split(torch, mg, classes, cls, act, x0, mult)
+        progress("split scheme timed")
     sim.close()
     del act
     torch.cuda.empty_cache()
@@ -824,13 +820,20 @@ def main():
         out["policy_in_the_loop"] = [bench_policy(torch, mg, n) for n in (4096, 1 << 16, 1 << 20)]
         out["policy_in_the_loop"] += [bench_policy(torch, mg, n, graph=True)
                                       for n in (4096, 1 << 16)]
+        progress("policy in the loop timed")
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, mg)
         out["adjoint_1m_envs"] = bench_adjoint(torch, mg, reps=3, n_envs=1 << 20)
+        progress("adjoint timed")
     if not args.no_serve:
-        cb = bench_serving(torch, mg, args.serve_seconds, steps_per_tick=8)
-        cb1 = bench_serving(torch, mg, args.serve_seconds, steps_per_tick=1)
-        base = bench_serving(torch, mg, args.serve_seconds, fifo_plain=True)
+        cb = bench_serving(torch, mg, args.serve_seconds, warmup_s=args.serve_warmup,
+                           steps_per_tick=8)
+        progress(f"serving (continuous batching) timed: p99 {cb['p99_ms']:.3f} ms")
+        cb1 = bench_serving(torch, mg, args.serve_aux_seconds, warmup_s=1.0, steps_per_tick=1)
+        progress("serving (one step per tick) timed")
+        base = bench_serving(torch, mg, args.serve_seconds, warmup_s=args.serve_warmup,
+                             fifo_plain=True)
+        progress(f"serving (FIFO baseline) timed: p99 {base['p99_ms']:.3f} ms")
         out["serving"] = {"continuous_batching": cb, "continuous_batching_1_step_per_tick": cb1,
                           "baseline_fifo_plain": base,
                           "p99_speedup_vs_baseline": base["p99_ms"] / cb["p99_ms"]}

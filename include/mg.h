@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define MG_ABI_VERSION 3u
+#define MG_ABI_VERSION 4u
 #define MG_MAX_THRUSTERS 8
 #define MG_MAX_CLASSES 16
 #define MG_NUM_PARAMS 23  /* m, Ixx, Iyy, Izz, M_A(6), D_L(6), D_Q(6), B */
@@ -377,7 +377,19 @@ mg_status mg_adj_backward_noalloc(mg_sim* sim, const float* ckpt, const float* a
  *   env_class        host [n_envs] class per env, or NULL (all class 0); copied at submit
  *   x0               device [D][ld] initial states (first n_envs columns)
  *   param_mult       device [23][ld] parameter multipliers, or NULL (nominal)
- *   actions          device [n_steps][N_max][ld] throttles
+ *   actions          device [n_steps][N_max][ld] throttles, or NULL with
+ *                    actions_from_seed
+ *   actions_from_seed 1: the throttles are generated on the device from
+ *                    action_seed instead of read (actions is ignored): throttle
+ *                    i of env e (0-based in the request) at control step t is
+ *                    2 u - 1, u = (z >> 40) 2^-24, where z is output number
+ *                    k = (t N_max + i) n_envs + e (0-based) of the SplitMix64
+ *                    generator seeded with action_seed, i.e.
+ *                    z = mix(action_seed + (k + 1) 0x9E3779B97F4A7C15) with
+ *                    mix: z ^= z >> 30; z *= 0xBF58476D1CE4E5B9; z ^= z >> 27;
+ *                    z *= 0x94D049BB133111EB; z ^= z >> 31 (Steele, Lea and
+ *                    Flood, OOPSLA 2014).  U[-1, 1) on a 2^-23 grid, exact in
+ *                    FP32.  0: read from actions.
  *   ld               column stride of x0, param_mult and actions (>= n_envs)
  *   out              host [D][n_envs]: the final states, written before completion
  *   arrival_ns       arrival stamp on the mg_clock_ns() clock, or 0 (= at submit;
@@ -404,7 +416,7 @@ typedef struct {
 typedef struct {
   int64_t n_envs;
   int32_t n_steps;
-  int32_t reserved;
+  int32_t actions_from_seed;
   const int32_t* env_class;
   const float* x0;
   const float* param_mult;
@@ -412,6 +424,7 @@ typedef struct {
   int64_t ld;
   float* out;
   uint64_t arrival_ns;
+  uint64_t action_seed;
 } mg_request;
 
 /* Server counters: requests completed / rejected, ticks issued, env control
@@ -436,7 +449,13 @@ mg_status mg_server_submit(mg_server* srv, const mg_request* req, uint64_t* tick
 /* Waits up to timeout_us (< 0: forever) for a ticket; MG_OK once its result is in
  * out (the ticket is then consumed and *latency_s, if not NULL, receives
  * arrival-to-completion seconds), MG_ERR_BUSY on timeout, MG_ERR_INVALID for an
- * unknown ticket, MG_ERR_DEVICE if the server failed. */
+ * unknown or already consumed ticket (also for a second thread waiting on a
+ * ticket that another waiter consumed meanwhile), MG_ERR_DEVICE if the server
+ * failed before the request completed: a failed tick fails every request in
+ * flight or queued, and every later submit.  Test hook: with the environment
+ * variable MG_SERVER_FAIL_TICK=n set when the server is created, the scheduler
+ * treats the completion of its n-th tick (n >= 1) as a device error, without
+ * any fault on the GPU. */
 mg_status mg_server_wait(mg_server* srv, uint64_t ticket, int64_t timeout_us, double* latency_s);
 mg_status mg_server_get_stats(const mg_server* srv, mg_server_stats* out);
 const char* mg_server_last_error(const mg_server* srv);

@@ -3,7 +3,8 @@
     python -m paper_2410_14117_amd.build
 
 Every .hip file under csrc/ is compiled to an object under _build/ and the
-objects are linked into paper_2410_14117_amd/libmg.so.  Packed FP32 math is
+objects are linked into paper_2410_14117_amd/libmg.so; the serving client
+driver (clients/replay.cpp, host code) becomes libmg_clients.so beside it.  Packed FP32 math is
 switched off (-packed-fp32-ops) for all device code.
 """
 import concurrent.futures as cf
@@ -16,6 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmg.so")
+CLIENTS_LIB = os.path.join(HERE, "libmg_clients.so")
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -60,7 +62,25 @@ def build(verbose=True, out=None, build_dir=None, defines=()):
     os.replace(tmp, lib)
     if verbose:
         print(f"built {lib} from {len(srcs)} sources")
+    if out is None:
+        build_clients(verbose)
     return lib
+
+
+def build_clients(verbose=True):
+    """The serving client driver (clients/replay.cpp) as libmg_clients.so, a host-only
+    library linked against libmg.so (found beside it at run time)."""
+    src = os.path.join(HERE, "clients", "replay.cpp")
+    tmp = CLIENTS_LIB + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-Wall", "-I",
+           os.path.join(ROOT, "include"), src, "-o", tmp, "-L", HERE, "-lmg",
+           "-Wl,-rpath,$ORIGIN", "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"client driver build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, CLIENTS_LIB)
+    if verbose:
+        print(f"built {CLIENTS_LIB}")
 
 
 if __name__ == "__main__":

@@ -36,6 +36,16 @@ __global__ void __launch_bounds__(64) k_serve_join(const ServeInitItem* __restri
     it.block[i * kPageEnvs + lane] = i < Dc ? it.x0[i * it.ld + col] : 0.0f;
 }
 
+// Output number k (0-based) of the SplitMix64 generator seeded with `seed`
+// (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+// OOPSLA 2014): the mixing function applied to seed + (k + 1) * gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // One page (64 envs, one per lane) of class constants cc: the request's
 // control steps [first, first + cnt) with the state in registers throughout.
 template <int N, bool LAG>
@@ -56,10 +66,21 @@ __device__ __forceinline__ void serve_page(const ServeTickItem& it, const ClassC
   const int64_t left = (int64_t)it.L - first;
   const int64_t cnt = a.steps < left ? (int64_t)a.steps : left;
   for (int64_t k = 0; k < cnt; ++k) {
-    const float* af = it.actions + (first + k) * a.n_max * it.ld + col;
     float act[N], fcmd[N], gcmd[6];
+    if (it.actions) {
+      const float* af = it.actions + (first + k) * a.n_max * it.ld + col;
 #pragma unroll
-    for (int i = 0; i < N; ++i) act[i] = af[i * it.ld];
+      for (int i = 0; i < N; ++i) act[i] = af[i * it.ld];
+    } else {
+      // throttle i of env col at control step t: generator output
+      // (t * n_max + i) * n + col, its top 24 bits as u in [0, 1), 2 u - 1
+      const uint64_t k0 = ((uint64_t)(first + k) * (uint64_t)a.n_max) * (uint64_t)it.n + col;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const uint64_t z = splitmix64_at(it.seed, k0 + (uint64_t)i * (uint64_t)it.n);
+        act[i] = fmaf((float)(uint32_t)(z >> 40), 0x1p-23f, -1.0f);
+      }
+    }
     thrust_command<N>(cc, act, fcmd);
     command_wrench<N>(cc, fcmd, gcmd);
     // substeps is the server's S (cc.rho_s = rho^S) or, for the FIFO plain
@@ -120,6 +141,8 @@ __global__ void __launch_bounds__(64) k_serve_leave(const ServeGatherItem* __res
     z.t0 = 0;
     z.L = 0;
     z.pad_ = 0;
+    z.seed = 0;
+    z.n = 0;
     list[it.list_index] = z;
   }
   const int64_t col = it.cols[lane];

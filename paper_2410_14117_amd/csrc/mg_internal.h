@@ -177,11 +177,13 @@ struct AdjArgs {
 struct ServeTickItem {         // one active page (device-resident list entry)
   float* block;                // NULL: an empty entry
   const int32_t* cols;
-  const float* actions;        // request [L][n_max][ld]
+  const float* actions;        // request [L][n_max][ld], or NULL: generated from seed
   int64_t ld;
   int64_t t0;                  // control-step clock when the request joined
   int32_t L;                   // control steps of the request
   int32_t pad_;
+  uint64_t seed;               // SplitMix64 seed of generated throttles
+  int64_t n;                   // env count of the request (generated throttles)
 };
 struct ServeInitItem {         // one newly admitted page
   float* block;

@@ -19,11 +19,13 @@
 #include "mg.h"
 #include "mg_internal.h"
 #include "page_pool.h"
+#include "serve_book.h"
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -55,7 +57,8 @@ struct Request {
   std::vector<int64_t> per_class;    // env count per class
   const float* x0 = nullptr;
   const float* mult = nullptr;
-  const float* actions = nullptr;
+  const float* actions = nullptr;    // NULL: throttles generated from seed
+  uint64_t seed = 0;
   int64_t ld = 0;
   float* out = nullptr;
   uint64_t arrival = 0;
@@ -64,12 +67,6 @@ struct Request {
   std::vector<int32_t> cols;         // [pages][64]
   std::vector<int32_t> entry;        // per page: its entry in the class's tick list
   int64_t t0 = 0;                    // tick of its first control step
-};
-
-struct Record {
-  uint64_t arrival = 0, done = 0;
-  mg_status status = MG_OK;
-  bool finished = false;
 };
 
 // Pinned host buffer mapped into the device's address space: the host writes
@@ -186,21 +183,14 @@ struct mg_server {
     Pinned<ServeGatherItem> gather;   // pages leaving after this tick
     OutBuffer* out = nullptr;     // pooled result buffer of this tick's finished requests
     hipEvent_t ev = nullptr;
+    int64_t seq = 0;                  // 1-based number of the tick in this slot
     std::vector<Request*> retiring;   // finished by this tick, delivered on completion
   };
-  // one piece of a finished request to deliver: floats [begin, end) of its
-  // states, which sit at src in the pinned side of a tick's result buffer that
-  // the tick's finished requests share.  Large results are cut into pieces of
-  // kDeliverChunk floats that the delivery threads copy in parallel; the
+  // Finished requests' states sit in the pinned side of a tick's result buffer
+  // that the tick's finished requests share; large results are cut into pieces
+  // of kDeliverChunk floats that the delivery threads copy in parallel; a
   // request completes with its last piece, and the tick's last piece returns
   // the buffer to the pool.
-  struct Delivery {
-    Request* r;
-    const float* src;
-    size_t begin, end;
-    OutBuffer* out;
-    std::shared_ptr<std::atomic<int>> pending_req, pending_tick;
-  };
   static constexpr size_t kDeliverChunk = (size_t)1 << 18;
   static constexpr int kDeliverThreads = 4;
   static constexpr int kSlots = 3;
@@ -218,27 +208,23 @@ struct mg_server {
   int32_t max_grid = 1024;            // blocks of the tick launch (4 pages each) at most
   ClassConst* cc_dev = nullptr;       // device copy of cc
 
-  // queue, records, thread
-  std::mutex mu;
-  std::condition_variable cv_sched, cv_done;
-  std::deque<Request*> queue;
+  // admission queue (with the stop and failure state), tickets, thread
+  std::unique_ptr<AdmissionQueue<Request>> queue;
+  TicketBook book;
+  std::mutex pool_mu;              // guards pool (scheduler admits, deliverers release)
   std::vector<Request*> active;    // scheduler thread only
-  std::unordered_map<uint64_t, Record> records;
-  uint64_t next_ticket = 1;
-  bool stop = false;
-  bool broken = false;
-  std::string err;
+  std::mutex err_mu;
+  std::string err;                 // first failure, kept for mg_server_last_error
+  int64_t fail_tick = 0;           // test hook: treat this tick's completion as failed
   std::thread thr;
   // delivery threads: copy finished requests' states to the clients, free their
   // pages and complete them, off the scheduler thread; a few of them, so that a
   // large result does not hold up the small ones finishing beside it
   std::thread deliver_thr[kDeliverThreads];
+  DeliveryQueue<Request, OutBuffer> deliveries;
   std::mutex dmu;
-  std::condition_variable dcv, dcv_done;
-  std::deque<Delivery> deliver_q;
   std::vector<OutBuffer*> out_pool;   // free pinned result buffers (guarded by dmu)
   std::vector<OutBuffer*> out_all;    // every result buffer, for teardown
-  bool deliver_stop = false;
 
   // statistics
   std::atomic<int64_t> completed{0}, rejected{0}, ticks{0}, env_steps{0}, active_envs{0},
@@ -250,9 +236,11 @@ struct mg_server {
 namespace {
 
 bool fail_server(mg_server* S, const std::string& msg) {
-  std::lock_guard<std::mutex> lk(S->mu);
-  S->broken = true;
-  S->err = msg;
+  {
+    std::lock_guard<std::mutex> lk(S->err_mu);
+    if (S->err.empty()) S->err = msg;
+  }
+  S->queue->fail(msg);
   return false;
 }
 
@@ -281,36 +269,9 @@ ClassNominal class_nominal(const mg_vehicle& v) {
 }
 
 void finish(mg_server* S, Request* r, mg_status st) {
-  const uint64_t t = clock_ns();
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    Record& rec = S->records[r->ticket];
-    rec.done = t;
-    rec.status = st;
-    rec.finished = true;
-  }
-  S->cv_done.notify_all();
   if (st == MG_OK) S->completed.fetch_add(1);
+  S->book.close(r->ticket, st, clock_ns());
   delete r;
-}
-
-// Deliver one piece of a request that finished in a completed tick: copy it
-// from the pinned result buffer to the client; with the request's last piece,
-// free its pages and complete it.
-void deliver(mg_server* S, mg_server::Delivery& d) {
-  Request* r = d.r;
-  std::memcpy(r->out + d.begin, d.src + d.begin, (d.end - d.begin) * sizeof(float));
-  if (d.pending_req->fetch_sub(1) == 1) {
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->pool->release(r->pages);
-    }
-    finish(S, r, MG_OK);
-  }
-  if (d.pending_tick->fetch_sub(1) == 1) {
-    std::lock_guard<std::mutex> lk(S->dmu);
-    S->out_pool.push_back(d.out);
-  }
 }
 
 OutBuffer* take_out_buffer(mg_server* S) {
@@ -410,6 +371,8 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
         it.item.t0 = r->t0;
         it.item.L = r->L;
         it.item.pad_ = 0;
+        it.item.seed = r->seed;
+        it.item.n = r->n;
         list_h[it.list_index] = it.item;
       }
     }
@@ -450,7 +413,7 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
   S->active_envs.store(envs);
   if (envs > S->max_active_envs.load()) S->max_active_envs.store(envs);
   S->env_steps.fetch_add(env_steps);
-  S->ticks.fetch_add(1);
+  sl.seq = S->ticks.fetch_add(1) + 1;
   S->tick_no += K;
 
   // 3. the requests whose last control step was in this tick
@@ -510,44 +473,41 @@ bool retire_oldest(mg_server* S, bool block, bool* took) {
   hipError_t e = block ? hipEventSynchronize(sl.ev) : hipEventQuery(sl.ev);
   if (block) S->wait_ns.fetch_add((int64_t)(clock_ns() - t_wait));
   if (e == hipErrorNotReady) return true;
+  if (e == hipSuccess && sl.seq == S->fail_tick)
+    return fail_server(S, "tick " + std::to_string(sl.seq) + ": failure injected by the host");
   if (e != hipSuccess) return fail_server(S, std::string("tick: ") + hipGetErrorString(e));
   S->inflight.pop_front();
   if (!sl.retiring.empty()) {
-    const size_t C = mg_server::kDeliverChunk;
-    int pieces = 0;
-    for (Request* r : sl.retiring) pieces += (int)(((size_t)r->n * S->D + C - 1) / C);
-    auto pending_tick = std::make_shared<std::atomic<int>>(pieces);
-    {
-      std::lock_guard<std::mutex> lk(S->dmu);
-      size_t o = 0;
-      for (Request* r : sl.retiring) {
-        const size_t len = (size_t)r->n * S->D;
-        auto pending_req = std::make_shared<std::atomic<int>>((int)((len + C - 1) / C));
-        for (size_t b = 0; b < len; b += C)
-          S->deliver_q.push_back(mg_server::Delivery{r, sl.out->h + o, b, std::min(len, b + C),
-                                                     sl.out, pending_req, pending_tick});
-        o += len;
-      }
-    }
+    std::vector<std::tuple<Request*, float*, size_t>> reqs;
+    reqs.reserve(sl.retiring.size());
+    for (Request* r : sl.retiring) reqs.emplace_back(r, r->out, (size_t)r->n * S->D);
+    S->deliveries.post(sl.out, sl.out->h, reqs, mg_server::kDeliverChunk);
     sl.retiring.clear();
     sl.out = nullptr;
-    S->dcv.notify_all();
   }
   *took = true;
   return true;
 }
 
+// Copies pieces of finished requests to their clients; with a request's last
+// piece frees its pages and completes it, with a tick's last piece returns
+// the tick's result buffer to the pool.
 void deliverer(mg_server* S) {
-  for (;;) {
-    mg_server::Delivery d;
-    {
-      std::unique_lock<std::mutex> lk(S->dmu);
-      S->dcv.wait(lk, [&] { return S->deliver_stop || !S->deliver_q.empty(); });
-      if (S->deliver_q.empty()) return;
-      d = std::move(S->deliver_q.front());
-      S->deliver_q.pop_front();
-    }
-    deliver(S, d);
+  DeliveryQueue<Request, OutBuffer>::Piece p;
+  while (S->deliveries.next(p)) {
+    DeliveryQueue<Request, OutBuffer>::deliver(
+        p,
+        [S](Request* r) {
+          {
+            std::lock_guard<std::mutex> lk(S->pool_mu);
+            S->pool->release(r->pages);
+          }
+          finish(S, r, MG_OK);
+        },
+        [S](OutBuffer* o) {
+          std::lock_guard<std::mutex> lk(S->dmu);
+          S->out_pool.push_back(o);
+        });
   }
 }
 
@@ -562,45 +522,39 @@ void scheduler(mg_server* S) {
     bool took = true;
     while (ok && took) ok = retire_oldest(S, false, &took);
     if (!ok) break;
-    {
-      std::unique_lock<std::mutex> lk(S->mu);
-      if (S->active.empty() && S->inflight.empty()) {
-        S->cv_sched.wait(lk, [&] { return S->stop || !S->queue.empty(); });
-        if (S->queue.empty() && S->stop) break;
-      }
-      // FIFO admission while the pages fit under the cap (FIFO baseline: one request
-      // at a time, the next admitted only once the previous one is delivered)
-      while (!S->queue.empty() && !S->broken) {
-        if (S->fifo_plain && (!S->active.empty() || !admitted.empty() || !S->inflight.empty()))
-          break;
-        Request* r = S->queue.front();
-        const int64_t need = PagePool::pages_for(r->per_class);
-        if (!S->pool->fits(need)) break;
-        std::vector<int64_t> pages;
-        if (!S->pool->allocate(need, pages)) {
-          // the cap allows it but device memory could not be obtained: with nothing
-          // in flight to free pages, this request cannot make progress
-          if (!S->active.empty() || !admitted.empty() || !S->inflight.empty()) break;
-          S->queue.pop_front();
+    if (S->active.empty() && S->inflight.empty() && !S->queue->wait_for_work()) break;
+    // FIFO admission while the pages fit under the cap (FIFO baseline: one request
+    // at a time, the next admitted only once the previous one is delivered)
+    using Admit = AdmissionQueue<Request>::Admit;
+    std::vector<Request*> dropped;
+    S->queue->admit(
+        [&](Request* r) {
+          const bool busy = !S->active.empty() || !admitted.empty() || !S->inflight.empty();
+          if (S->fifo_plain && busy) return Admit::Hold;
+          const int64_t need = PagePool::pages_for(r->per_class);
+          std::vector<int64_t> pages;
+          {
+            std::lock_guard<std::mutex> lk(S->pool_mu);
+            if (!S->pool->fits(need)) return Admit::Hold;
+            if (!S->pool->allocate(need, pages)) {
+              // the cap allows it but device memory could not be obtained: with
+              // nothing in flight to free pages, this request cannot make progress
+              if (busy) return Admit::Hold;
+              S->queued.fetch_sub(1);
+              return Admit::Drop;
+            }
+          }
           S->queued.fetch_sub(1);
-          lk.unlock();
-          finish(S, r, MG_ERR_OOM);
-          lk.lock();
-          continue;
-        }
-        S->queue.pop_front();
-        S->queued.fetch_sub(1);
-        {
           const int64_t qw = (int64_t)(clock_ns() - r->arrival);
           S->queue_ns.fetch_add(qw);
           S->admitted_n.fetch_add(1);
           if (qw > S->max_queue_ns.load()) S->max_queue_ns.store(qw);
-        }
-        r->pages = pages;
-        admitted.push_back(r);
-      }
-      if (S->broken) break;
-    }
+          r->pages = pages;
+          return Admit::Take;
+        },
+        admitted, dropped);
+    for (Request* r : dropped) finish(S, r, MG_ERR_OOM);
+    if (S->queue->failed()) break;
     if (admitted.empty() && S->active.empty()) {
       // nothing to issue: wait for the oldest tick in flight (if any)
       if (!S->inflight.empty()) ok = retire_oldest(S, true, &took);
@@ -622,17 +576,13 @@ void scheduler(mg_server* S) {
     S->inflight.push_back(k);
   }
   // drain: anything left fails (device error or shutdown)
-  const mg_status st = S->broken ? MG_ERR_DEVICE : MG_ERR_BUSY;
-  if (!S->broken) {
+  if (!S->queue->failed()) {
     bool took = true;
     while (!S->inflight.empty() && took && retire_oldest(S, true, &took)) {
     }
   }
-  {
-    std::lock_guard<std::mutex> lk(S->dmu);
-    S->deliver_stop = true;
-  }
-  S->dcv.notify_all();
+  const mg_status st = S->queue->failed() ? MG_ERR_DEVICE : MG_ERR_BUSY;
+  S->deliveries.stop();
   for (auto& t : S->deliver_thr)
     if (t.joinable()) t.join();
   for (int k : S->inflight) {
@@ -643,12 +593,10 @@ void scheduler(mg_server* S) {
   for (Request* r : admitted) finish(S, r, st);
   for (Request* r : S->active) finish(S, r, st);
   S->active.clear();
-  std::deque<Request*> q;
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    q.swap(S->queue);
+  for (Request* r : S->queue->take_all()) {
+    S->queued.fetch_sub(1);
+    finish(S, r, st);
   }
-  for (Request* r : q) finish(S, r, st);
 }
 
 }  // namespace
@@ -658,7 +606,9 @@ extern "C" {
 uint64_t mg_clock_ns(void) { return clock_ns(); }
 
 const char* mg_server_last_error(const mg_server* S) {
-  return S ? S->err.c_str() : g_server_create_error.c_str();
+  if (!S) return g_server_create_error.c_str();
+  std::lock_guard<std::mutex> lk(const_cast<mg_server*>(S)->err_mu);
+  return S->err.c_str();
 }
 
 mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
@@ -701,6 +651,8 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   S->fifo_plain = cfg->fifo_plain != 0;
   S->steps_per_tick = cfg->steps_per_tick > 1 ? cfg->steps_per_tick : 1;
   S->max_queue = cfg->max_queue > 0 ? cfg->max_queue : 65536;
+  S->queue = std::make_unique<AdmissionQueue<Request>>((size_t)S->max_queue);
+  if (const char* ft = std::getenv("MG_SERVER_FAIL_TICK")) S->fail_tick = std::atoll(ft);
   for (int k = 0; k < cfg->n_classes; ++k) {
     const mg_vehicle& v = cfg->classes[k];
     S->cc.push_back(make_class_const(v, cfg->dt_sub, cfg->substeps));
@@ -819,8 +771,9 @@ static void layout_pages(Request* r, int n_classes) {
 
 mg_status mg_server_submit(mg_server* S, const mg_request* req, uint64_t* ticket) {
   if (!S || !req || !ticket) return MG_ERR_INVALID;
-  if (req->n_envs < 1 || req->n_steps < 1 || !req->x0 || !req->actions || !req->out ||
-      req->ld < req->n_envs)
+  if (req->n_envs < 1 || req->n_steps < 1 || !req->x0 || !req->out || req->ld < req->n_envs ||
+      (req->actions_from_seed != 0 && req->actions_from_seed != 1) ||
+      (!req->actions_from_seed && !req->actions))
     return MG_ERR_INVALID;
   auto r = std::make_unique<Request>();
   r->n = req->n_envs;
@@ -834,49 +787,35 @@ mg_status mg_server_submit(mg_server* S, const mg_request* req, uint64_t* ticket
   }
   r->x0 = req->x0;
   r->mult = req->param_mult;
-  r->actions = req->actions;
+  r->actions = req->actions_from_seed ? nullptr : req->actions;
+  r->seed = req->action_seed;
   r->ld = req->ld;
   r->out = req->out;
   // an arrival stamp in the future (a client submitting early) counts from submission
   const uint64_t now = clock_ns();
   r->arrival = (req->arrival_ns && req->arrival_ns < now) ? req->arrival_ns : now;
+  // the cap is fixed at creation, so this test needs no lock
   const int64_t need = PagePool::pages_for(r->per_class);
-  if (need <= S->pool->cap_pages()) layout_pages(r.get(), S->n_classes);
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    if (S->broken) return MG_ERR_DEVICE;
-    if (S->stop) return MG_ERR_BUSY;
-    if (!S->pool->ever_fits(need)) {
-      S->rejected.fetch_add(1);
-      return MG_ERR_INVALID;
-    }
-    if ((int64_t)S->queue.size() >= S->max_queue) return MG_ERR_BUSY;
-    r->ticket = S->next_ticket++;
-    Record rec;
-    rec.arrival = r->arrival;
-    S->records[r->ticket] = rec;
-    *ticket = r->ticket;
-    S->queue.push_back(r.release());
-    S->queued.fetch_add(1);
+  if (!S->pool->ever_fits(need)) {
+    if (S->queue->failed()) return MG_ERR_DEVICE;
+    S->rejected.fetch_add(1);
+    return MG_ERR_INVALID;
   }
-  S->cv_sched.notify_one();
+  layout_pages(r.get(), S->n_classes);
+  Request* raw = r.get();
+  const mg_status st = S->queue->push(raw, [&](Request* q) {
+    q->ticket = S->book.open(q->arrival);
+    S->queued.fetch_add(1);
+  });
+  if (st != MG_OK) return st;
+  r.release();
+  *ticket = raw->ticket;
   return MG_OK;
 }
 
 mg_status mg_server_wait(mg_server* S, uint64_t ticket, int64_t timeout_us, double* latency_s) {
   if (!S) return MG_ERR_INVALID;
-  std::unique_lock<std::mutex> lk(S->mu);
-  auto it = S->records.find(ticket);
-  if (it == S->records.end()) return MG_ERR_INVALID;
-  auto ready = [&] { return S->records[ticket].finished; };
-  if (timeout_us < 0)
-    S->cv_done.wait(lk, ready);
-  else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
-    return MG_ERR_BUSY;
-  Record rec = S->records[ticket];
-  S->records.erase(ticket);
-  if (latency_s) *latency_s = (double)(rec.done - rec.arrival) * 1e-9;
-  return rec.status;
+  return S->book.wait(ticket, timeout_us, latency_s);
 }
 
 mg_status mg_server_get_stats(const mg_server* S, mg_server_stats* out) {
@@ -897,22 +836,14 @@ mg_status mg_server_get_stats(const mg_server* S, mg_server_stats* out) {
   out->max_queue_ns = S->max_queue_ns.load();
   out->max_issue_ns = S->max_issue_ns.load();
   out->grow_events = S->grow_events.load();
-  return S->broken ? MG_ERR_DEVICE : MG_OK;
+  return S->queue && S->queue->failed() ? MG_ERR_DEVICE : MG_OK;
 }
 
 void mg_server_destroy(mg_server* S) {
   if (!S) return;
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->stop = true;
-  }
-  S->cv_sched.notify_all();
+  if (S->queue) S->queue->stop();
   if (S->thr.joinable()) S->thr.join();
-  {
-    std::lock_guard<std::mutex> lk(S->dmu);
-    S->deliver_stop = true;
-  }
-  S->dcv.notify_all();
+  S->deliveries.stop();
   for (auto& t : S->deliver_thr)
     if (t.joinable()) t.join();
   (void)hipSetDevice(S->device);

@@ -12,7 +12,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MG_LIBRARY") or os.path.join(HERE, "libmg.so")
 
-MG_ABI_VERSION = 3
+MG_ABI_VERSION = 4
 MAX_THR = 8
 NUM_PARAMS = 23
 NUM_THETA = 19
@@ -91,10 +91,11 @@ def task_struct(task):
 
 class MgRequest(ctypes.Structure):
     _fields_ = [
-        ("n_envs", ctypes.c_int64), ("n_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_envs", ctypes.c_int64), ("n_steps", ctypes.c_int32),
+        ("actions_from_seed", ctypes.c_int32),
         ("env_class", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("param_mult", ctypes.c_void_p),
         ("actions", ctypes.c_void_p), ("ld", ctypes.c_int64), ("out", ctypes.c_void_p),
-        ("arrival_ns", ctypes.c_uint64),
+        ("arrival_ns", ctypes.c_uint64), ("action_seed", ctypes.c_uint64),
     ]
 
 
@@ -166,6 +167,26 @@ def lib():
             raise ImportError("libmg ABI version mismatch")
         _lib = L
     return _lib
+
+
+_clients = None
+
+
+def clients_lib():
+    """The serving client driver, libmg_clients.so (built beside libmg.so)."""
+    global _clients
+    if _clients is None:
+        lib()
+        path = os.path.join(os.path.dirname(LIB_PATH), "libmg_clients.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with "
+                              "`python -m paper_2410_14117_amd.build`")
+        L = ctypes.CDLL(path)
+        L.mgc_replay.restype = ctypes.c_int
+        L.mgc_replay.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, _vp, _vp,
+                                 ctypes.POINTER(MgRequest), ctypes.c_uint64, _vp, _vp, _vp]
+        _clients = L
+    return _clients
 
 
 def vehicle_struct(preset):
@@ -496,10 +517,11 @@ class Server:
         return lib().mg_clock_ns()
 
     def submit(self, n_envs, n_steps, x0_ptr, actions_ptr, ld, out, env_class=None,
-               mult_ptr=None, arrival_ns=0):
+               mult_ptr=None, arrival_ns=0, action_seed=None):
         """Device pointers x0 [D][ld], actions [n_steps][N_max][ld], mult [23][ld] (optional);
-        out: host float32 array [D][n_envs] that receives the final states.  Returns
-        (status, ticket)."""
+        out: host float32 array [D][n_envs] that receives the final states.  With
+        action_seed (an unsigned 64-bit int) the throttles are generated on the device from
+        it and actions_ptr is ignored.  Returns (status, ticket)."""
         if out.dtype != np.float32 or out.shape != (self.state_dim, n_envs) or \
                 not out.flags["C_CONTIGUOUS"]:
             raise ValueError("out must be a contiguous float32 [D][n_envs] host array")
@@ -514,7 +536,11 @@ class Server:
         r.env_class = ec.ctypes.data if ec is not None else None
         r.x0 = int(x0_ptr)
         r.param_mult = int(mult_ptr) if mult_ptr else None
-        r.actions = int(actions_ptr)
+        if action_seed is None:
+            r.actions = int(actions_ptr)
+        else:
+            r.actions_from_seed = 1
+            r.action_seed = int(action_seed) & 0xFFFFFFFFFFFFFFFF
         r.ld = int(ld)
         r.out = out.ctypes.data
         r.arrival_ns = int(arrival_ns)
@@ -534,6 +560,55 @@ class Server:
             with self._lock:
                 self._keep.pop(ticket, None)
         return st, lat.value
+
+    def replay(self, requests, t0_ns, n_clients):
+        """Replays an arrival trace from n_clients native client threads (libmg_clients.so,
+        mgc_replay): request i is submitted by client requests[i]["client"] at
+        t0_ns + requests[i]["at_ns"], stamped with that arrival, and waited for by the same
+        thread.  Each request is a dict with client, at_ns, n_envs, n_steps, x0_ptr, ld, out
+        (host [D][n_envs] float32), and optionally env_class, mult_ptr, actions_ptr or
+        action_seed.  Returns (status [n] int32, latency_s [n], submit lag ns [n])."""
+        n = len(requests)
+        reqs = (MgRequest * max(1, n))()
+        client = np.zeros(max(1, n), np.int32)
+        at = np.zeros(max(1, n), np.uint64)
+        keep = []
+        for i, q in enumerate(requests):
+            out = q["out"]
+            if out.dtype != np.float32 or out.shape != (self.state_dim, q["n_envs"]) or \
+                    not out.flags["C_CONTIGUOUS"]:
+                raise ValueError("out must be a contiguous float32 [D][n_envs] host array")
+            r = reqs[i]
+            r.n_envs = int(q["n_envs"])
+            r.n_steps = int(q["n_steps"])
+            ec = q.get("env_class")
+            if ec is not None:
+                ec = np.ascontiguousarray(np.asarray(ec, dtype=np.int32))
+                keep.append(ec)
+                r.env_class = ec.ctypes.data
+            r.x0 = int(q["x0_ptr"])
+            r.param_mult = int(q["mult_ptr"]) if q.get("mult_ptr") else None
+            if q.get("action_seed") is not None:
+                r.actions_from_seed = 1
+                r.action_seed = int(q["action_seed"]) & 0xFFFFFFFFFFFFFFFF
+            else:
+                r.actions = int(q["actions_ptr"])
+            r.ld = int(q["ld"])
+            r.out = out.ctypes.data
+            client[i] = int(q["client"])
+            at[i] = int(q["at_ns"])
+        status = np.zeros(max(1, n), np.int32)
+        lat = np.zeros(max(1, n), np.float64)
+        lag = np.zeros(max(1, n), np.int64)
+        rc = clients_lib().mgc_replay(self._h, int(n_clients), n, client.ctypes.data,
+                                      at.ctypes.data, reqs, int(t0_ns), status.ctypes.data,
+                                      lat.ctypes.data, lag.ctypes.data)
+        if rc != 0:
+            raise ValueError("mgc_replay rejected its arguments")
+        return status[:n], lat[:n], lag[:n]
+
+    def last_error(self):
+        return (lib().mg_server_last_error(self._h) or b"").decode()
 
     def stats(self):
         s = MgServerStats()

@@ -25,6 +25,17 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_client_driver_exports_every_declared_symbol():
+    text = open(os.path.join(ROOT, "include", "mg_clients.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(mgc_[a-z_]+)\s*\(", text)))
+    assert names == ["mgc_replay"]
+    L = mg.clients_lib()
+    assert all(hasattr(L, n) for n in names)
+    # bad arguments are refused before anything is submitted
+    assert L.mgc_replay(None, 1, 0, None, None, None, 0, None, None, None) == -1
+
+
 def test_abi_version_and_status_strings():
     L = mg.lib()
     assert L.mg_abi_version() == mg.MG_ABI_VERSION

@@ -13,6 +13,7 @@ import pytest
 
 from workloads import (BLUEROV2, BLUEROV2_HEAVY, vehicle_variant, initial_state, actions,
                        param_multipliers, env_classes)
+from workloads.gen import splitmix64_throttles
 from tests.gpu_util import dev, host, rel_err, say, TOL_TRAJ
 
 pytestmark = pytest.mark.gpu
@@ -344,3 +345,138 @@ def test_c5_trace_in_the_benchmark_configuration(mgmod):
         sim.step(dev(act[:L, :, off:off + n]))
         np.testing.assert_array_equal(host(sim.get_state()), out)
         sim.close()
+
+
+def test_seed_mode_equals_pointer_mode(mgmod, pools):
+    """Requests whose throttles the tick kernel generates from a seed (SplitMix64) give,
+    bitwise, the final states of the same requests with those throttles generated on the
+    host and passed by pointer; 12 requests of both classes, 1 to 64 control steps, served
+    together in each mode at 8 control steps per tick."""
+    rng = np.random.default_rng(431)
+    reqs = []
+    for k in range(12):
+        n = int(np.exp(rng.uniform(np.log(16), np.log(6000))))
+        reqs.append((int(rng.integers(0, POOL - n)), n, int(rng.integers(1, LMAX + 1)),
+                     int(rng.integers(0, 2 ** 63)) * 2 + 1))
+    srv = mgmod.Server(CLASSES, DT, S, steps_per_tick=8)
+    say("serve seed mode: 12 requests, throttles generated on the device")
+    seeded, tickets = [], []
+    for off, n, L, seed in reqs:
+        out = np.zeros((D, n), np.float32)
+        r = _req(pools, off, n, L)
+        r["actions_ptr"] = 0
+        st, t = srv.submit(out=out, action_seed=seed, **r)
+        assert st == 0
+        seeded.append(out)
+        tickets.append(t)
+    for t in tickets:
+        assert srv.wait(t, 60_000_000)[0] == 0
+    say("serve pointer mode: the same throttles generated on the host")
+    keep, tickets, ptr = [], [], []
+    for off, n, L, seed in reqs:
+        a = dev(splitmix64_throttles(seed, L, NMAX, n))
+        keep.append(a)
+        out = np.zeros((D, n), np.float32)
+        # the host throttles have column stride n, so x0 and the multipliers are passed
+        # as copies of the request's columns with that stride too
+        x0c = dev(pools["x0"][:, off:off + n])
+        mc = dev(pools["mult"][:, off:off + n])
+        keep += [x0c, mc]
+        st, t = srv.submit(n, L, x0c.data_ptr(), a.data_ptr(), n, out,
+                           env_class=pools["cls"][off:off + n], mult_ptr=mc.data_ptr())
+        assert st == 0
+        ptr.append(out)
+        tickets.append(t)
+    for t in tickets:
+        assert srv.wait(t, 60_000_000)[0] == 0
+    srv.close()
+    for a, b in zip(seeded, ptr):
+        assert np.isfinite(a).all()
+        np.testing.assert_array_equal(a, b)
+
+
+def test_two_waiters_on_one_ticket(mgmod, pools):
+    """Two threads wait on one ticket: exactly one receives the result (MG_OK), the other
+    MG_ERR_INVALID (the ticket was consumed), neither blocks for ever."""
+    srv = mgmod.Server(CLASSES, DT, S)
+    out = np.zeros((D, 3000), np.float32)
+    say("serve two waiters on one ticket")
+    st, tk = srv.submit(out=out, **_req(pools, 100, 3000, 64))
+    assert st == 0
+    got = []
+    lock = threading.Lock()
+
+    def waiter():
+        r = srv.wait(tk, 60_000_000)[0]
+        with lock:
+            got.append(r)
+
+    ths = [threading.Thread(target=waiter) for _ in range(2)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join(90)
+    assert sorted(got) == [0, 1]
+    srv.close()
+
+
+def test_injected_tick_failure_fails_every_request_in_flight(mgmod, pools, monkeypatch):
+    """With MG_SERVER_FAIL_TICK=3 the scheduler treats its third tick's completion as a
+    device error (set on the host; nothing faults on the GPU): every request not yet
+    delivered completes with MG_ERR_DEVICE, none hangs, later submits are refused with
+    MG_ERR_DEVICE, and the server still shuts down cleanly."""
+    monkeypatch.setenv("MG_SERVER_FAIL_TICK", "3")
+    srv = mgmod.Server(CLASSES, DT, S)
+    monkeypatch.delenv("MG_SERVER_FAIL_TICK")
+    say("serve injected failure at tick 3: 10 rollouts of 64 steps")
+    subs = []
+    for k in range(10):
+        out = np.zeros((D, 500), np.float32)
+        st, tk = srv.submit(out=out, **_req(pools, 600 * k, 500, 64))
+        assert st == 0
+        subs.append(tk)
+    res = [srv.wait(tk, 60_000_000)[0] for tk in subs]
+    assert set(res) == {3}                       # MG_ERR_DEVICE, all of them (64 > 3 ticks)
+    out = np.zeros((D, 16), np.float32)
+    assert srv.submit(out=out, **_req(pools, 0, 16, 1))[0] == 3
+    assert "injected" in srv.last_error()
+    srv.close()
+
+
+def test_native_clients_replay(mgmod, pools):
+    """32 native client threads (libmg_clients.so) replay a 0.4 s Poisson trace at 2000
+    req/s with seed-generated throttles, submitting concurrently: every request completes
+    with finite states, latencies are positive, and two of the requests equal, bitwise, the
+    same requests served alone afterwards."""
+    rng = np.random.default_rng(441)
+    reqs = []
+    for k in range(32):
+        t = 0.0
+        while True:
+            t += rng.exponential(32 / 2000.0)
+            if t > 0.4:
+                break
+            n = int(round(np.exp(rng.uniform(np.log(16), np.log(8192)))))
+            L = 1 if rng.random() < 0.5 else int(rng.integers(1, LMAX + 1))
+            off = int(rng.integers(0, POOL - n + 1))
+            reqs.append({"client": k, "at_ns": int(t * 1e9), "n_envs": n, "n_steps": L,
+                         "x0_ptr": pools["x0_d"].data_ptr() + 4 * off, "ld": POOL,
+                         "out": np.zeros((D, n), np.float32),
+                         "env_class": pools["cls"][off:off + n],
+                         "mult_ptr": pools["mult_d"].data_ptr() + 4 * off,
+                         "action_seed": int(rng.integers(0, 2 ** 63)), "off": off})
+    srv = mgmod.Server(CLASSES, DT, S, steps_per_tick=8)
+    say(f"serve native replay: {len(reqs)} requests from 32 client threads")
+    status, lat, lag = srv.replay(reqs, mgmod.Server.clock_ns() + 20_000_000, 32)
+    assert (status == 0).all() and (lat > 0).all()
+    for q in reqs:
+        assert np.isfinite(q["out"]).all()
+    for q in (reqs[0], reqs[len(reqs) // 2]):
+        out = np.zeros_like(q["out"])
+        st, tk = srv.submit(q["n_envs"], q["n_steps"], q["x0_ptr"], 0, POOL, out,
+                            env_class=q["env_class"], mult_ptr=q["mult_ptr"],
+                            action_seed=q["action_seed"])
+        assert st == 0 and srv.wait(tk, 60_000_000)[0] == 0
+        np.testing.assert_array_equal(out, q["out"])
+    assert srv.stats()["completed"] == len(reqs) + 2
+    srv.close()

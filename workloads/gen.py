@@ -151,3 +151,19 @@ def env_classes(n_envs, kind, seed=None):
         r = np.random.Generator(np.random.PCG64(seed))
         return (r.random(n_envs) < 0.5).astype(np.int32)
     raise ValueError(kind)
+
+
+def splitmix64_throttles(seed, n_steps, n_max, n_envs):
+    """[T][N_max][E] FP32 throttles of a serving request whose actions are generated from a
+    seed: throttle i of env e at control step t is 2 u - 1 with u = (z >> 40) 2^-24, z the
+    SplitMix64 output number (t N_max + i) E + e of the generator seeded with `seed`
+    (Steele, Lea and Flood, OOPSLA 2014: output k = mix(seed + (k + 1) gamma))."""
+    gamma = np.uint64(0x9E3779B97F4A7C15)
+    k = np.arange(n_steps * n_max * n_envs, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (k + np.uint64(1)) * gamma
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(40)).astype(np.float32) * np.float32(2.0 ** -24)
+    return (u * np.float32(2.0) - np.float32(1.0)).reshape(n_steps, n_max, n_envs)

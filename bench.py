@@ -332,13 +332,25 @@ def bench_serving(torch, mg, duration_s=30.0, fifo_plain=False, seed=5005, warmu
         wall = time.perf_counter() - w0 - 0.05
         ok = status == 0
         env_steps = sum(r[2] * r[3] for r, o in zip(trace, ok) if o)
-        return lat[ok], env_steps, wall, lag, int((~ok).sum())
+        # requests slower than 10 ms, grouped into episodes by arrival (gaps < 50 ms)
+        slow = sorted((trace[i][1], float(lat[i])) for i in range(len(trace))
+                      if ok[i] and lat[i] > 0.01)
+        episodes = []
+        for t, l in slow:
+            if episodes and t - episodes[-1][1] < 0.05:
+                e = episodes[-1]
+                episodes[-1] = (e[0], t, e[2] + 1, max(e[3], l))
+            else:
+                episodes.append((t, t, 1, l))
+        slow_summary = [{"from_s": round(a, 4), "to_s": round(b, 4), "requests": n,
+                         "max_ms": round(m * 1e3, 2)} for a, b, n, m in episodes[:20]]
+        return lat[ok], env_steps, wall, lag, int((~ok).sum()), slow_summary
 
     if warmup_s > 0:
         run(make_trace(warmup_s, seed + 1))
     s0 = srv.stats()
     trace = make_trace(duration_s, seed)
-    lats, env_steps, wall, lags, failed = run(trace)
+    lats, env_steps, wall, lags, failed, slow = run(trace)
     s1 = srv.stats()
     srv.close()
     ticks = max(1, s1["ticks"] - s0["ticks"])
@@ -363,7 +375,10 @@ def bench_serving(torch, mg, duration_s=30.0, fifo_plain=False, seed=5005, warmu
             "queue_wait_max_ms_incl_warmup": s1["max_queue_ns"] / 1e6,
             "max_tick_issue_ms_incl_warmup": s1["max_issue_ns"] / 1e6,
             "staging_growths": s1["grow_events"] - s0["grow_events"],
+            "held_joins": s1["held_joins"] - s0["held_joins"],
+            "deferred_retires": s1["deferred_retires"] - s0["deferred_retires"],
             "pages_created": s1["created_pages"] - s0["created_pages"],
+            "slow_episodes": slow,
             "submit_lag_p50_ms": float(np.percentile(lags, 50) / 1e6),
             "submit_lag_p99_ms": float(np.percentile(lags, 99) / 1e6)}
 

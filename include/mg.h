@@ -358,11 +358,14 @@ mg_status mg_adj_backward_noalloc(mg_sim* sim, const float* ckpt, const float* a
  *   max_queue      bound of the admission queue (0 -> 65536)
  *   reserve_bytes  page memory (>= 0) to create at start (at most the cap),
  *                  with pinned staging for up to 4096 pages joining or
- *                  leaving per tick and 16 pinned result buffers of up to
- *                  16 MB, so that serving within it allocates nothing; 0:
- *                  pages are created on demand in slabs of 1024 and staging
- *                  grows as needed.  Creation fails with MG_ERR_OOM if the
- *                  reservation cannot be had.
+ *                  leaving per tick, 16 pinned result buffers of up to 16 MB
+ *                  and a tick list for every reserved page, so that serving
+ *                  within it allocates nothing: joins and retirements beyond
+ *                  a tick's staging wait for a later tick instead (a request
+ *                  larger than the staging alone still grows it); 0: pages
+ *                  are created on demand in slabs of 1024 and staging grows as
+ *                  needed.  Creation fails with MG_ERR_OOM if the reservation
+ *                  cannot be had.
  *   steps_per_tick most control steps (0 -> 1, at most 64) a page advances per
  *                  tick: each active request advances min(steps_per_tick,
  *                  steps it has left), its states held in registers across
@@ -432,12 +435,16 @@ typedef struct {
  * and pages created; host time spent issuing ticks and blocked waiting for the
  * GPU (ns, summed); mean and max time from arrival to admission (ns); the
  * longest host time spent issuing one tick (ns); how many times a staging
- * buffer had to grow (each growth allocates). */
+ * buffer had to grow (each growth allocates); with reserve_bytes, how many
+ * times a join waited a tick because the tick's join staging was full, and how
+ * many finished requests waited a tick to retire because the tick's result
+ * staging was full (a reserved server allocates nothing for a request that
+ * fits its staging alone). */
 typedef struct {
   int64_t completed, rejected, ticks, env_steps, active_envs, max_active_envs, queued;
   int64_t cap_pages, created_pages;
   int64_t issue_ns, wait_ns, mean_queue_ns, max_queue_ns;
-  int64_t max_issue_ns, grow_events;
+  int64_t max_issue_ns, grow_events, held_joins, deferred_retires;
 } mg_server_stats;
 
 uint64_t mg_clock_ns(void);

@@ -60,8 +60,8 @@ __device__ __forceinline__ void serve_page(const ServeTickItem& it, const ClassC
   for (int i = 0; i < D; ++i) x[i] = it.block[i * kPageEnvs + lane];
   const EnvConst P = load_env_const(it.block + a.Dmax * kPageEnvs, kPageEnvs, lane);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
-  // the host keeps a page in the list only while first < L, so the action rows
-  // read stay below L
+  // rows t < L only: a page whose request has done its L control steps and
+  // waits in the list for room to retire gets cnt <= 0 and is left as it is
   const int64_t first = a.tick - it.t0;
   const int64_t left = (int64_t)it.L - first;
   const int64_t cnt = a.steps < left ? (int64_t)a.steps : left;

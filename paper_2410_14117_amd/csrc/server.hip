@@ -158,6 +158,11 @@ struct mg_server {
   bool fifo_plain = false;
   int32_t steps_per_tick = 1;        // most control steps a page advances per tick
   int64_t max_queue = 65536;
+  // with a reservation, a tick joins at most stage_pages pages and retires at
+  // most stage_pages pages and out_floats result floats (beyond a single
+  // request); the rest waits a tick, so that serving allocates nothing
+  bool reserved = false;
+  size_t stage_pages = 0, out_floats = 0;
   std::vector<ClassConst> cc;
   std::vector<ClassNominal> nominal;
   ClassNominal* nominal_dev = nullptr;
@@ -230,7 +235,7 @@ struct mg_server {
   std::atomic<int64_t> completed{0}, rejected{0}, ticks{0}, env_steps{0}, active_envs{0},
       max_active_envs{0}, queued{0};
   std::atomic<int64_t> issue_ns{0}, wait_ns{0}, queue_ns{0}, max_queue_ns{0}, admitted_n{0};
-  std::atomic<int64_t> max_issue_ns{0}, grow_events{0};
+  std::atomic<int64_t> max_issue_ns{0}, grow_events{0}, held_joins{0}, deferred_retires{0};
 };
 
 namespace {
@@ -274,13 +279,16 @@ void finish(mg_server* S, Request* r, mg_status st) {
   delete r;
 }
 
-OutBuffer* take_out_buffer(mg_server* S) {
+// A free result buffer from the pool; a new (empty) one if the pool is empty
+// and allow_new, else NULL.
+OutBuffer* take_out_buffer(mg_server* S, bool allow_new) {
   std::lock_guard<std::mutex> lk(S->dmu);
   if (!S->out_pool.empty()) {
     OutBuffer* m = S->out_pool.back();
     S->out_pool.pop_back();
     return m;
   }
+  if (!allow_new) return nullptr;
   S->out_all.push_back(new OutBuffer());
   return S->out_all.back();
 }
@@ -416,20 +424,41 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
   sl.seq = S->ticks.fetch_add(1) + 1;
   S->tick_no += K;
 
-  // 3. the requests whose last control step was in this tick
+  // 3. the requests that have done their last control step retire, as many as
+  // the reserved staging holds (always at least one); the others stay in the
+  // tick list without work (their pages' step count is spent) until a later
+  // tick has room
   std::vector<Request*> keep;
+  size_t n_gat = 0, n_out = 0;
   for (Request* r : S->active) {
     r->step += (int32_t)std::min<int64_t>(K, r->L - r->step);
-    (r->step >= r->L ? sl.retiring : keep).push_back(r);
-  }
-  S->active.swap(keep);
-  size_t n_gat = 0, n_out = 0;
-  for (Request* r : sl.retiring) {
-    n_gat += r->pages.size();
-    n_out += (size_t)r->n * S->D;
+    if (r->step < r->L) {
+      keep.push_back(r);
+      continue;
+    }
+    const size_t g = r->pages.size(), o = (size_t)r->n * S->D;
+    if (S->reserved && !sl.retiring.empty() &&
+        (n_gat + g > S->stage_pages || n_out + o > S->out_floats)) {
+      keep.push_back(r);
+      S->deferred_retires.fetch_add(1);
+      continue;
+    }
+    sl.retiring.push_back(r);
+    n_gat += g;
+    n_out += o;
   }
   if (!sl.retiring.empty()) {
-    sl.out = take_out_buffer(S);
+    sl.out = take_out_buffer(S, !S->reserved);
+    if (!sl.out) {
+      // every reserved result buffer is still being delivered from
+      S->deferred_retires.fetch_add((int64_t)sl.retiring.size());
+      keep.insert(keep.end(), sl.retiring.begin(), sl.retiring.end());
+      sl.retiring.clear();
+      n_gat = n_out = 0;
+    }
+  }
+  S->active.swap(keep);
+  if (!sl.retiring.empty()) {
     if (!grow_counted(S, sl.gather, n_gat) || !grow_counted(S, *sl.out, n_out))
       return fail_server(S, "pinned result allocation failed");
     size_t k = 0, o = 0;
@@ -527,11 +556,18 @@ void scheduler(mg_server* S) {
     // at a time, the next admitted only once the previous one is delivered)
     using Admit = AdmissionQueue<Request>::Admit;
     std::vector<Request*> dropped;
+    int64_t join_pages = 0;
+    for (Request* r : admitted) join_pages += (int64_t)r->pages.size();
     S->queue->admit(
         [&](Request* r) {
           const bool busy = !S->active.empty() || !admitted.empty() || !S->inflight.empty();
           if (S->fifo_plain && busy) return Admit::Hold;
           const int64_t need = PagePool::pages_for(r->per_class);
+          // a reserved server joins at most its staging's pages per tick
+          if (S->reserved && !admitted.empty() && join_pages + need > (int64_t)S->stage_pages) {
+            S->held_joins.fetch_add(1);
+            return Admit::Hold;
+          }
           std::vector<int64_t> pages;
           {
             std::lock_guard<std::mutex> lk(S->pool_mu);
@@ -550,6 +586,7 @@ void scheduler(mg_server* S) {
           S->admitted_n.fetch_add(1);
           if (qw > S->max_queue_ns.load()) S->max_queue_ns.store(qw);
           r->pages = pages;
+          join_pages += need;
           return Admit::Take;
         },
         admitted, dropped);
@@ -700,7 +737,10 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   }
   S->free_entries.resize(S->n_classes);
   S->hw.assign(S->n_classes, 0);
-  S->list_cap = 8192;   // entries per class (64 envs each); grows by doubling
+  // tick-list entries per class (64 envs each); grows by doubling, so a
+  // reservation sizes it for every reserved page
+  S->list_cap = (size_t)std::max<int64_t>(
+      8192, std::min<int64_t>(cap_pages, std::max<int64_t>(0, cfg->reserve_bytes) / page_bytes));
   {
     std::vector<ServeTickItem> z(S->list_cap * S->n_classes);
     std::memset(z.data(), 0, z.size() * sizeof(ServeTickItem));
@@ -735,6 +775,9 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
       S->out_pool.push_back(S->out_all.back());
       ok = S->out_all.back()->grow(out_floats);
     }
+    S->reserved = true;
+    S->stage_pages = items;
+    S->out_floats = out_floats;
     if (!ok) {
       mg_server_destroy(S.release());
       return bad(MG_ERR_OOM, "could not reserve the requested page memory and staging");
@@ -836,6 +879,8 @@ mg_status mg_server_get_stats(const mg_server* S, mg_server_stats* out) {
   out->max_queue_ns = S->max_queue_ns.load();
   out->max_issue_ns = S->max_issue_ns.load();
   out->grow_events = S->grow_events.load();
+  out->held_joins = S->held_joins.load();
+  out->deferred_retires = S->deferred_retires.load();
   return S->queue && S->queue->failed() ? MG_ERR_DEVICE : MG_OK;
 }
 

@@ -103,7 +103,8 @@ class MgServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("completed", "rejected", "ticks", "env_steps", "active_envs", "max_active_envs",
                  "queued", "cap_pages", "created_pages", "issue_ns", "wait_ns", "mean_queue_ns",
-                 "max_queue_ns", "max_issue_ns", "grow_events")]
+                 "max_queue_ns", "max_issue_ns", "grow_events", "held_joins",
+                 "deferred_retires")]
 
 
 _vp = ctypes.c_void_p

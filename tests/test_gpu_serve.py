@@ -480,3 +480,52 @@ def test_native_clients_replay(mgmod, pools):
         np.testing.assert_array_equal(out, q["out"])
     assert srv.stats()["completed"] == len(reqs) + 2
     srv.close()
+
+
+def test_reserved_staging_defers_instead_of_growing(mgmod):
+    """A server reserved with 4096 pages (4096 pages of join and leave staging per tick,
+    result buffers of 2^22 floats, 32 sub-steps per control step, 64 control steps per
+    tick).  A blocker of 190 000 envs x 64 control steps (about 3000 pages, 4.0e6 result
+    floats: within the staging) keeps the GPU busy for a few milliseconds while six
+    requests of 50 000 envs x 1 step queue up: five join together (about 3910 pages), the
+    sixth waits for the next tick (join staging full), and of the five, which all finish in
+    that tick, three retire at once and the others a tick later (results beyond 2^22
+    floats).  No staging grows, and every result equals, bitwise, the same request served
+    alone on an unreserved server."""
+    P, n, S32 = 1 << 18, 50000, 32
+    cls = env_classes(P, "bernoulli", 451)
+    x0 = initial_state(P, D, 452)
+    x0[19:, cls == 0] = 0
+    x0_d, mult_d = dev(x0), dev(param_multipliers(P, 0.2, 453))
+    offs = [7919 * k for k in range(6)]
+
+    def submit(srv, off, m, L, seed):
+        out = np.zeros((D, m), np.float32)
+        st, tk = srv.submit(m, L, x0_d.data_ptr() + 4 * off, 0, P, out,
+                            env_class=cls[off:off + m], mult_ptr=mult_d.data_ptr() + 4 * off,
+                            action_seed=seed)
+        assert st == 0
+        return tk, out
+
+    srv = mgmod.Server(CLASSES, DT / 8, S32, steps_per_tick=64,
+                       reserve_bytes=4096 * mgmod.page_bytes(D))
+    s0 = srv.stats()
+    say("serve reserved staging: blocker of 190000 envs, then 6 x 50000 envs")
+    tb, _ = submit(srv, 0, 190000, 64, 1)
+    while srv.stats()["ticks"] == s0["ticks"]:
+        pass
+    subs = [submit(srv, off, n, 1, 100 + k) for k, off in enumerate(offs)]
+    assert srv.wait(tb, 60_000_000)[0] == 0
+    for tk, _ in subs:
+        assert srv.wait(tk, 60_000_000)[0] == 0
+    s1 = srv.stats()
+    srv.close()
+    assert s1["grow_events"] == s0["grow_events"]
+    assert s1["held_joins"] > s0["held_joins"]
+    assert s1["deferred_retires"] > s0["deferred_retires"]
+    ref = mgmod.Server(CLASSES, DT / 8, S32, steps_per_tick=64)
+    for k, off in enumerate(offs):
+        tk, out = submit(ref, off, n, 1, 100 + k)
+        assert ref.wait(tk, 60_000_000)[0] == 0
+        np.testing.assert_array_equal(out, subs[k][1])
+    ref.close()

@@ -24,6 +24,8 @@ __host__ __device__ inline double abs_t(double a) { return fabs(a); }
 // reciprocal square root (v_rsq_f32, 1 ulp) without the denormal rescaling
 // rsqrtf wraps around it, which gives the same value for normal inputs.
 __device__ inline float rsqrt_t(float a) { return __builtin_amdgcn_rsqf(a); }
+// host overload (CPU checks of the FP32 code): correctly rounded sqrt, then divide
+__host__ inline float rsqrt_t(float a) { return 1.0f / sqrtf(a); }
 __host__ __device__ inline double rsqrt_t(double a) { return 1.0 / sqrt(a); }
 
 // Per-env constants held in registers for the whole launch.

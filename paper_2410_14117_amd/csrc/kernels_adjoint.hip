@@ -8,6 +8,7 @@
 //               the segment's sub-step states from its checkpoint into a
 //               scratch buffer, then sweeps the sub-step VJPs backwards,
 //               emitting dL/d throttle per step and accumulating dL/d theta.
+//               Its per-env body is adj_bwd_env (fossen_adjoint.h).
 #include "fossen_adjoint.h"
 
 namespace mg {
@@ -26,58 +27,6 @@ namespace mg {
 #else
 #define MG_ADJ_FWD_ATTR
 #endif
-
-template <int N>
-__device__ __forceinline__ void load_command(const ClassConst& cc, const AdjArgs& a, int t,
-                                             int64_t c, float (&act)[N], float (&fcmd)[N],
-                                             float (&gcmd)[6]) {
-  const float* af = a.actions + (int64_t)t * a.n_max * a.E + c;
-#pragma unroll
-  for (int i = 0; i < N; ++i) act[i] = af[i * a.E];
-  thrust_command<N>(cc, act, fcmd);
-  command_wrench<N>(cc, fcmd, gcmd);
-}
-
-// Recomputes the sub-step inputs of control steps [t0, t1) from the state x
-// at t0 into segbuf rows (t - base) * S + s.  The forward sets the lag states
-// to their end-of-control-step value at the start; the sub-step inputs the VJP
-// linearises about carry the lag states of each sub-step, f_cmd + rho^s
-// (f - f_cmd), kept here in fs.
-// Used by k_adj_recompute only: k_adj_bwd keeps its own copy of this loop
-// (see there).
-template <int N, bool LAG>
-__device__ __forceinline__ void recompute_segment(const AdjArgs& a, const ClassConst& cc,
-                                                  const EnvConst& P, const HalfInvT<float>& A,
-                                                  const StepConstT<float>& sc,
-                                                  float (&x)[Dims<N, LAG>::D], int t0, int t1,
-                                                  int base, int64_t j, int64_t c) {
-  constexpr int D = Dims<N, LAG>::D;
-  const int S = a.substeps;
-  for (int t = t0; t < t1; ++t) {
-    float act[N], fcmd[N], gcmd[6], dg[6], fs[LAG ? N : 1];
-    load_command<N>(cc, a, t, c, act, fcmd, gcmd);
-    if constexpr (LAG) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) fs[i] = x[13 + i];
-    }
-    begin_control_step<N, LAG>(cc, x, fcmd, dg, cc.rho_s);
-    float m[6];
-    momentum(P, x + 7, m);
-    for (int s = 0; s < S; ++s) {
-      float* sb = a.segbuf + (int64_t)((t - base) * S + s) * D * a.Ep + j;
-#pragma unroll
-      for (int i = 0; i < 13; ++i) sb[i * a.Ep] = x[i];
-      if constexpr (LAG) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          sb[(13 + i) * a.Ep] = fs[i];
-          fs[i] = fma_t(sc.rho, fs[i] - fcmd[i], fcmd[i]);
-        }
-      }
-      rk4_substep<N, LAG>(x, m, P, A, gcmd, dg, sc);
-    }
-  }
-}
 
 template <int N, bool LAG>
 __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_fwd(const AdjArgs a, const ClassConst cc) {
@@ -130,18 +79,9 @@ __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_fwd(const AdjArg
   for (int i = 0; i < D; ++i) a.state[i * a.Ep + j] = x[i];
 }
 
-// WHOLE: the sub-step inputs of the whole rollout are already in segbuf
-// (k_adj_recompute); otherwise each segment is recomputed here, into a
-// segment-sized segbuf, just before its sweep.  The recomputation loop is
-// written out here rather than calling recompute_segment: with that call
-// inlined, the one-wave 8-thruster lag instantiation (256 VGPRs + AGPRs)
-// returned gradients 5e-2 away from the oracle's although the source was
-// equivalent, and out of line the call's register saves made the kernel 2-3x
-// slower; this loop, unchanged, matches the oracle to 5e-7.
 template <int N, bool LAG, int WAVES, bool WHOLE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAVES)))
 k_adj_bwd(const AdjArgs a, const ClassConst cc) {
-  constexpr int D = Dims<N, LAG>::D;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;
   const int64_t j = a.seg_start + local;
@@ -149,88 +89,7 @@ k_adj_bwd(const AdjArgs a, const ClassConst cc) {
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
-  const int K = a.ckpt_every, S = a.substeps;
-  const int nseg = (a.T + K - 1) / K;
-  float lam[D];
-#pragma unroll
-  for (int i = 0; i < D; ++i) lam[i] = 0.0f;
-  ThetaBar<float> thb;
-  theta_bar_zero(thb);
-  for (int seg = nseg - 1; seg >= 0; --seg) {
-    const int t0 = seg * K, t1 = min(a.T, t0 + K);
-    const int base = WHOLE ? 0 : t0;   // segbuf row of control step t: (t - base) * S
-    if constexpr (!WHOLE) {
-      // recompute this segment's sub-step inputs from its checkpoint
-      float x[D];
-      const float* ck = a.ckpt + (int64_t)seg * a.D * a.E + c;
-#pragma unroll
-      for (int i = 0; i < D; ++i) x[i] = ck[i * a.E];
-      // (the forward sets the lag states to their end-of-control-step value at
-      // the start; the sub-step inputs the VJP linearises about carry the lag
-      // states of each sub-step, f_cmd + rho^s (f - f_cmd), kept here in fs)
-      for (int t = t0; t < t1; ++t) {
-        float act[N], fcmd[N], gcmd[6], dg[6], fs[LAG ? N : 1];
-        load_command<N>(cc, a, t, c, act, fcmd, gcmd);
-        if constexpr (LAG) {
-#pragma unroll
-          for (int i = 0; i < N; ++i) fs[i] = x[13 + i];
-        }
-        begin_control_step<N, LAG>(cc, x, fcmd, dg, cc.rho_s);
-        float m[6];
-        momentum(P, x + 7, m);
-        for (int s = 0; s < S; ++s) {
-          float* sb = a.segbuf + (int64_t)((t - t0) * S + s) * D * a.Ep + j;
-#pragma unroll
-          for (int i = 0; i < 13; ++i) sb[i * a.Ep] = x[i];
-          if constexpr (LAG) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-              sb[(13 + i) * a.Ep] = fs[i];
-              fs[i] = fma_t(sc.rho, fs[i] - fcmd[i], fcmd[i]);
-            }
-          }
-          rk4_substep<N, LAG>(x, m, P, A, gcmd, dg, sc);
-        }
-      }
-    }
-    // reverse sweep over the segment
-    for (int t = t1 - 1; t >= t0; --t) {
-      const float* gt = a.gtraj + (int64_t)t * a.D * a.E + c;
-#pragma unroll
-      for (int i = 0; i < D; ++i) lam[i] += gt[i * a.E];
-      float act[N], fcmd[N], gcmd[6], fcb[N], gcb[6], ab[N];
-      load_command<N>(cc, a, t, c, act, fcmd, gcmd);
-#pragma unroll
-      for (int i = 0; i < N; ++i) fcb[i] = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) gcb[k] = 0.0f;
-      for (int s = S - 1; s >= 0; --s) {
-        float y[D];
-        const float* sb = a.segbuf + (int64_t)((t - base) * S + s) * D * a.Ep + j;
-#pragma unroll
-        for (int i = 0; i < D; ++i) y[i] = sb[i * a.Ep];
-        rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
-      }
-      throttle_vjp<N>(cc, act, fcb, gcb, ab);
-      float* ga = a.gact + (int64_t)t * a.n_max * a.E + c;
-#pragma unroll
-      for (int i = 0; i < N; ++i) ga[i * a.E] = ab[i];
-      for (int i = N; i < a.n_max; ++i) ga[i * a.E] = 0.0f;
-    }
-  }
-  // theta = (M_A(6), D_L(6), D_Q(6), B);  W - B and h_z = W z_g - B z_b carry B
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    a.gtheta[i * a.E + c] = thb.ma[i];
-    a.gtheta[(6 + i) * a.E + c] = thb.dl[i];
-    a.gtheta[(12 + i) * a.E + c] = thb.dq[i];
-  }
-  a.gtheta[18 * a.E + c] = -thb.wmb - a.zb * thb.hz;
-  if (a.gx0) {
-#pragma unroll
-    for (int i = 0; i < D; ++i) a.gx0[i * a.E + c] = lam[i];
-    for (int i = D; i < a.D; ++i) a.gx0[i * a.E + c] = 0.0f;
-  }
+  adj_bwd_env<N, LAG, WHOLE>(a, cc, P, sc, A, j, c);
 }
 
 // Every segment's recomputation at once (blockIdx.y = segment) into the

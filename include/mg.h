@@ -34,7 +34,8 @@
  *              MG_ERR_INVALID with no side effect.  A failed HIP call makes
  *              the sim sticky: it and every later call return MG_ERR_DEVICE.
  *              An env whose state becomes non-finite is not an error: it is
- *              counted in the episode statistics and keeps propagating NaN.
+ *              frozen and flagged (mg_get_flags) and counted in the episode
+ *              statistics, and the rest of the batch steps on.
  *              mg_last_error() gives a text for the last failure.
  *   Threads    a sim is thread-compatible (one thread at a time); distinct
  *              sims may be used from distinct threads.
@@ -63,6 +64,7 @@ typedef int32_t mg_status;
 #define MG_ERR_DEVICE 3      /* a HIP call failed; the sim is unusable */
 #define MG_ERR_UNSUPPORTED 4 /* valid description this GPU path does not implement */
 #define MG_ERR_BUSY 5        /* server queue full / request not finished */
+#define MG_ERR_CANCELLED 6   /* server request cancelled by mg_server_cancel */
 
 typedef struct mg_sim mg_sim;
 
@@ -141,8 +143,13 @@ int64_t mg_num_envs(const mg_sim* sim);       /* E, or -1 */
  *               parameters, or NULL (nominal).  Here the per-env mass matrix
  *               M = M_RB + M_A and its inverse are formed once (in FP64,
  *               rounded to FP32) and kept for every later step; an env whose
- *               M is not positive definite gets NaN constants and shows up as
- *               non-finite after its next step. */
+ *               M is not positive definite (or whose parameters are not
+ *               finite) gets NaN constants and the flag MG_FLAG_NOT_SPD, and
+ *               is frozen until a reset gives it valid parameters.  The
+ *               non-finite flag of every env whose state is written is
+ *               cleared.  The check runs on the device, so mg_reset stays
+ *               asynchronous and does not return MG_ERR_INVALID for it: read
+ *               the flags to find such envs. */
 mg_status mg_reset(mg_sim* sim, const int64_t* env_ids, int64_t n_ids, const float* state,
                    const float* param_mult);
 /* Physical-parameter domain randomisation given as absolute values (Sec. II,
@@ -152,9 +159,22 @@ mg_status mg_reset(mg_sim* sim, const int64_t* env_ids, int64_t n_ids, const flo
 mg_status mg_set_params(mg_sim* sim, const float* params);
 /* Sets the pose eta and body velocity nu of Eq. (1) (Sec. II; as the
  * quaternion state described above) and the thruster states of every env
- * from device [D][E]; parameters are kept.  Together with mg_get_state this
- * is a bitwise-exact save and resume.  NULL state: MG_ERR_INVALID. */
+ * from device [D][E]; parameters are kept, MG_FLAG_NONFINITE is cleared.
+ * Together with mg_get_state this is a bitwise-exact save and resume.  NULL
+ * state: MG_ERR_INVALID. */
 mg_status mg_set_state(mg_sim* sim, const float* state);
+
+/* Per-env status of the environment instances (Sec. II): int32 [E], caller
+ * env order, to out (out_on_device != 0: device pointer, enqueued; 0: host,
+ * synchronous).  Bits: MG_FLAG_NONFINITE -- the state went non-finite in a
+ * step (mg_step, mg_step_plain, mg_rollout), the env is frozen;
+ * MG_FLAG_NOT_SPD -- the parameters of the last reset give a mass matrix that
+ * is not positive definite, the env is frozen.  A Gym task step that restarts
+ * an env clears its MG_FLAG_NONFINITE (and re-derives MG_FLAG_NOT_SPD when it
+ * restarts with new multipliers).  NULL out: MG_ERR_INVALID. */
+#define MG_FLAG_NONFINITE 1
+#define MG_FLAG_NOT_SPD 2
+mg_status mg_get_flags(mg_sim* sim, int32_t* out, int32_t out_on_device);
 
 /* Advances every env by n_ctrl control steps in ONE fused launch per class:
  * each control step reads one throttle frame, holds it for `substeps` RK4
@@ -163,11 +183,21 @@ mg_status mg_set_state(mg_sim* sim, const float* state);
  *   actions  device [n_ctrl][N_max][E] throttles (rows >= a class's n_thr are ignored)
  *   targets  device [3][E] station-keeping targets for the statistics, or NULL (origin)
  *   traj     device [n_ctrl][D][E] state after each control step, or NULL
- *   stats    device double [n_ctrl][4] per control step, over envs with a
- *            finite state: sum and max of |p - target| (the Task-1 error of
+ *   stats    device double [n_ctrl][4] per control step, over envs that are
+ *            not frozen: sum and max of |p - target| (the Task-1 error of
  *            Eq. (4)), sum of kinetic energy 1/2 nu^T M nu; and the number of
- *            envs whose state is not finite.  Deterministic (fixed-order
- *            two-pass reduction).  Or NULL. */
+ *            frozen envs.  Deterministic (fixed-order two-pass reduction).  Or
+ *            NULL.
+ * Frozen envs: an env with a status flag set (mg_get_flags) is not stepped:
+ * its state, and its traj rows, stay as they are.  An env whose state is not
+ * finite at the end of a launch keeps the state it had when that launch began
+ * -- with one control step per launch (mg_rollout, mg_step with n_ctrl = 1)
+ * its last finite state -- and gets MG_FLAG_NONFINITE, so it is frozen from
+ * the next launch on until mg_reset or mg_set_state gives it a new state; the
+ * traj rows that launch wrote keep the non-finite values.  The other envs are
+ * not affected.  The
+ * split scheme (mg_step_split), the adjoint and the server neither read nor
+ * set the flags: there a non-finite state propagates NaN. */
 mg_status mg_step(mg_sim* sim, const float* actions, int32_t n_ctrl, const float* targets,
                   float* traj, double* stats);
 /* The sub-simulation steps of Sec. II (the paragraph after Eq. (1)) taken one
@@ -464,6 +494,14 @@ mg_status mg_server_submit(mg_server* srv, const mg_request* req, uint64_t* tick
  * treats the completion of its n-th tick (n >= 1) as a device error, without
  * any fault on the GPU. */
 mg_status mg_server_wait(mg_server* srv, uint64_t ticket, int64_t timeout_us, double* latency_s);
+/* Thread-safe.  Cancels a request that has not completed: a queued one leaves
+ * the queue at once, an admitted one is retired at the scheduler's next tick
+ * without its states being delivered, its pages freed; either then completes
+ * with MG_ERR_CANCELLED (mg_server_wait).  A request that has already done
+ * its last control step completes normally instead.  MG_OK when the
+ * cancellation is registered, MG_ERR_INVALID for an unknown or completed
+ * ticket. */
+mg_status mg_server_cancel(mg_server* srv, uint64_t ticket);
 mg_status mg_server_get_stats(const mg_server* srv, mg_server_stats* out);
 const char* mg_server_last_error(const mg_server* srv);
 /* Stops accepting requests, finishes every request already submitted, joins

@@ -366,7 +366,12 @@ __host__ __device__ __forceinline__ void recompute_segment(const AdjArgs& a, con
 // its constants P, the step factors sc and the pre-scaled inverse A.  Host and
 // device code, so that the same source also runs on the CPU (tests); the
 // kernel k_adj_bwd below loads the env's constants and inlines it.
-template <int N, bool LAG, bool WHOLE>
+// PREFETCH: the next sub-step's input and the next control step's dL/d traj
+// and throttles are loaded one step ahead, so that their latency hides
+// behind the current sub-step's VJP (a launch of one wave per SIMD has no
+// other wave to hide it behind); it costs 2 D + N registers, which the
+// two-wave build cannot spare.
+template <int N, bool LAG, bool WHOLE, bool PREFETCH = false>
 __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const ClassConst& cc,
                                                      const EnvConst& P,
                                                      const StepConstT<float>& sc,
@@ -418,28 +423,81 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
       }
     }
     // reverse sweep over the segment
-    for (int t = t1 - 1; t >= t0; --t) {
-      const float* gt = a.gtraj + (int64_t)t * a.D * a.E + c;
+    if constexpr (PREFETCH) {
+      float y_n[D], gt_n[D], act_n[N];
+      {
+        const float* sb = a.segbuf + (int64_t)((t1 - 1 - base) * S + S - 1) * D * a.Ep + j;
 #pragma unroll
-      for (int i = 0; i < D; ++i) lam[i] += gt[i * a.E];
-      float act[N], fcmd[N], gcmd[6], fcb[N], gcb[6], ab[N];
-      load_command<N>(cc, a, t, c, act, fcmd, gcmd);
+        for (int i = 0; i < D; ++i) y_n[i] = sb[i * a.Ep];
+        const float* gt = a.gtraj + (int64_t)(t1 - 1) * a.D * a.E + c;
 #pragma unroll
-      for (int i = 0; i < N; ++i) fcb[i] = 0.0f;
+        for (int i = 0; i < D; ++i) gt_n[i] = gt[i * a.E];
+        const float* af = a.actions + (int64_t)(t1 - 1) * a.n_max * a.E + c;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) gcb[k] = 0.0f;
-      for (int s = S - 1; s >= 0; --s) {
-        float y[D];
-        const float* sb = a.segbuf + (int64_t)((t - base) * S + s) * D * a.Ep + j;
-#pragma unroll
-        for (int i = 0; i < D; ++i) y[i] = sb[i * a.Ep];
-        rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
+        for (int i = 0; i < N; ++i) act_n[i] = af[i * a.E];
       }
-      throttle_vjp<N>(cc, act, fcb, gcb, ab);
-      float* ga = a.gact + (int64_t)t * a.n_max * a.E + c;
+      for (int t = t1 - 1; t >= t0; --t) {
+        float act[N], fcmd[N], gcmd[6], fcb[N], gcb[6], ab[N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) ga[i * a.E] = ab[i];
-      for (int i = N; i < a.n_max; ++i) ga[i * a.E] = 0.0f;
+        for (int i = 0; i < D; ++i) lam[i] += gt_n[i];
+#pragma unroll
+        for (int i = 0; i < N; ++i) act[i] = act_n[i];
+        if (t > t0) {
+          const float* gt = a.gtraj + (int64_t)(t - 1) * a.D * a.E + c;
+#pragma unroll
+          for (int i = 0; i < D; ++i) gt_n[i] = gt[i * a.E];
+          const float* af = a.actions + (int64_t)(t - 1) * a.n_max * a.E + c;
+#pragma unroll
+          for (int i = 0; i < N; ++i) act_n[i] = af[i * a.E];
+        }
+        thrust_command<N>(cc, act, fcmd);
+        command_wrench<N>(cc, fcmd, gcmd);
+#pragma unroll
+        for (int i = 0; i < N; ++i) fcb[i] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) gcb[k] = 0.0f;
+        for (int s = S - 1; s >= 0; --s) {
+          float y[D];
+#pragma unroll
+          for (int i = 0; i < D; ++i) y[i] = y_n[i];
+          if (s > 0 || t > t0) {
+            const int row = s > 0 ? (t - base) * S + s - 1 : (t - 1 - base) * S + S - 1;
+            const float* sb = a.segbuf + (int64_t)row * D * a.Ep + j;
+#pragma unroll
+            for (int i = 0; i < D; ++i) y_n[i] = sb[i * a.Ep];
+          }
+          rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
+        }
+        throttle_vjp<N>(cc, act, fcb, gcb, ab);
+        float* ga = a.gact + (int64_t)t * a.n_max * a.E + c;
+#pragma unroll
+        for (int i = 0; i < N; ++i) ga[i * a.E] = ab[i];
+        for (int i = N; i < a.n_max; ++i) ga[i * a.E] = 0.0f;
+      }
+    } else {
+      for (int t = t1 - 1; t >= t0; --t) {
+        const float* gt = a.gtraj + (int64_t)t * a.D * a.E + c;
+#pragma unroll
+        for (int i = 0; i < D; ++i) lam[i] += gt[i * a.E];
+        float act[N], fcmd[N], gcmd[6], fcb[N], gcb[6], ab[N];
+        load_command<N>(cc, a, t, c, act, fcmd, gcmd);
+#pragma unroll
+        for (int i = 0; i < N; ++i) fcb[i] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) gcb[k] = 0.0f;
+        for (int s = S - 1; s >= 0; --s) {
+          float y[D];
+          const float* sb = a.segbuf + (int64_t)((t - base) * S + s) * D * a.Ep + j;
+#pragma unroll
+          for (int i = 0; i < D; ++i) y[i] = sb[i * a.Ep];
+          rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
+        }
+        throttle_vjp<N>(cc, act, fcb, gcb, ab);
+        float* ga = a.gact + (int64_t)t * a.n_max * a.E + c;
+#pragma unroll
+        for (int i = 0; i < N; ++i) ga[i * a.E] = ab[i];
+        for (int i = N; i < a.n_max; ++i) ga[i * a.E] = 0.0f;
+      }
     }
   }
   // theta = (M_A(6), D_L(6), D_Q(6), B);  W - B and h_z = W z_g - B z_b carry B

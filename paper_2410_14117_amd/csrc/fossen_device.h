@@ -142,7 +142,9 @@ __device__ __forceinline__ void derive_constants(const double (&prm)[kNumParams]
 // each rounded once to FP32 and stored, and the factorisation derived from
 // the stored FP32 values (so a sim restored from its parameters reproduces
 // the original bitwise).
-__device__ __forceinline__ void set_env_params(const ClassNominal& nom, const float* in,
+// Returns false when the mass matrix is not positive definite (or a parameter
+// is not finite): the derived constants are then NaN.
+__device__ __forceinline__ bool set_env_params(const ClassNominal& nom, const float* in,
                                                int64_t stride, bool absolute, float* params,
                                                float* derived, int64_t Ep, int64_t j) {
   double prm[kNumParams];
@@ -159,8 +161,13 @@ __device__ __forceinline__ void set_env_params(const ClassNominal& nom, const fl
   }
   float dvf[kNumDerived];
   derive_constants(prm, nom.zg, nom.zb, dvf);
+  bool ok = true;
 #pragma unroll
-  for (int i = 0; i < kNumDerived; ++i) derived[i * Ep + j] = dvf[i];
+  for (int i = 0; i < kNumDerived; ++i) {
+    derived[i * Ep + j] = dvf[i];
+    ok = ok && isfinite(dvf[i]);
+  }
+  return ok;
 }
 
 // Row-plus-lane addressing for the step kernel.  A row pointer that is the

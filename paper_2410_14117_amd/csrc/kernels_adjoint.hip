@@ -89,7 +89,7 @@ k_adj_bwd(const AdjArgs a, const ClassConst cc) {
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
-  adj_bwd_env<N, LAG, WHOLE>(a, cc, P, sc, A, j, c);
+  adj_bwd_env<N, LAG, WHOLE, WAVES == 1>(a, cc, P, sc, A, j, c);
 }
 
 // Every segment's recomputation at once (blockIdx.y = segment) into the

@@ -70,10 +70,15 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
 
   float x[D];
   EnvConst P;
+  // an env whose flags are set is frozen: it is not stepped; an env whose
+  // state is non-finite at the end of the launch gets its launch-input state
+  // back and is flagged, so that it is frozen from the next launch on
+  bool frozen = false;
   if (active) {
 #pragma unroll
     for (int i = 0; i < D; ++i) x[i] = lane_elem(a.state + i * a.Ep, jo);
     P = load_env_const_off(a.derived, a.Ep, jo);
+    frozen = lane_elem(a.flags, (uint32_t)j) != 0;
   }
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
@@ -86,7 +91,8 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
       for (int i = 0; i < N; ++i) act[i] = lane_elem(af + i * a.E, co);
       thrust_command<N>(cc, act, fcmd);
       command_wrench<N>(cc, fcmd, gcmd);
-      control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, substeps, PLAIN ? cc.rho : cc.rho_s);
+      if (!frozen)
+        control_step<N, LAG>(x, P, A, cc, fcmd, gcmd, sc, substeps, PLAIN ? cc.rho : cc.rho_s);
       if (a.traj) {
         float* tf = a.traj + (int64_t)t * a.D * a.E;
 #pragma unroll
@@ -94,7 +100,7 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
         for (int i = D; i < a.D; ++i) lane_elem(tf + i * a.E, co) = 0.0f;
       }
       if (a.partials) {
-        bool finite = true;
+        bool finite = !frozen;
 #pragma unroll
         for (int i = 0; i < D; ++i) finite = finite && isfinite(x[i]);
         if (finite) {
@@ -126,8 +132,17 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
                   a.partials + ((int64_t)t * a.nblk_total + a.blk_off + blockIdx.x) * 4);
   }
   if (active) {
+    bool finite = true;
 #pragma unroll
-    for (int i = 0; i < D; ++i) lane_elem(a.state + i * a.Ep, jo) = x[i];
+    for (int i = 0; i < D; ++i) finite = finite && isfinite(x[i]);
+    if (finite) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) lane_elem(a.state + i * a.Ep, jo) = x[i];
+    } else {
+      // the launch-input state stays in place
+      lane_elem(a.flags, (uint32_t)j) =
+          (uint8_t)(lane_elem(a.flags, (uint32_t)j) | kFlagNonFinite);
+    }
   }
 }
 
@@ -204,8 +219,12 @@ __global__ void __launch_bounds__(256) k_reset(const ResetArgs a) {
   if (id < 0 || id >= a.E) return;
   const int64_t j = a.iperm ? (int64_t)a.iperm[id] : id;
   const ClassNominal& nom = a.nominal[a.class_of[j]];
-  set_env_params(nom, a.param_in ? a.param_in + k : nullptr, a.n, a.param_absolute != 0,
-                 a.params, a.derived, a.Ep, j);
+  const bool spd = set_env_params(nom, a.param_in ? a.param_in + k : nullptr, a.n,
+                                  a.param_absolute != 0, a.params, a.derived, a.Ep, j);
+  if (a.flags) {
+    const uint8_t keep = a.write_state ? 0 : (uint8_t)(a.flags[j] & kFlagNonFinite);
+    a.flags[j] = (uint8_t)(keep | (spd ? 0 : kFlagNotSPD));
+  }
   if (a.write_state && a.task_k) a.task_k[j] = 0;
   if (a.write_state && a.split_acc)
     for (int i = 0; i < 6; ++i) a.split_acc[i * a.Ep + j] = 0.0f;
@@ -251,6 +270,37 @@ __global__ void k_scatter_in(const float* __restrict__ in, int64_t E, float* __r
   const int64_t c = perm ? (int64_t)perm[j] : j;
   if (c < 0 || c >= E) return;
   for (int r = 0; r < rows; ++r) out[r * Ep + j] = in[r * E + c];
+}
+
+// status flags, internal bytes -> caller int32
+__global__ void k_flags_out(const uint8_t* __restrict__ flags, int32_t* __restrict__ out,
+                            int64_t E, const int32_t* __restrict__ perm, int64_t n_internal) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_internal) return;
+  const int64_t c = perm ? (int64_t)perm[j] : j;
+  if (c < 0 || c >= E) return;
+  out[c] = flags[j];
+}
+
+// flags &= mask for every env
+__global__ void k_flags_mask(uint8_t* __restrict__ flags, int64_t n, uint8_t mask) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) flags[j] = (uint8_t)(flags[j] & mask);
+}
+
+hipError_t launch_flags_out(const uint8_t* flags, int32_t* out, int64_t E, const int32_t* perm,
+                            int64_t n_internal, hipStream_t s) {
+  if (n_internal <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flags_out, dim3((unsigned)((n_internal + 255) / 256)), dim3(256), 0, s,
+                     flags, out, E, perm, n_internal);
+  return hipGetLastError();
+}
+
+hipError_t launch_flags_mask(uint8_t* flags, int64_t n, uint8_t mask, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_flags_mask, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, flags, n,
+                     mask);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather_out(const float* in, int64_t Ep, float* out, int64_t E, int32_t rows,

@@ -163,8 +163,11 @@ k_task(const TaskArgs a, const ClassConst cc, const TaskConst tc) {
         x[i] = a.reset_state ? a.reset_state[i * a.E + c] : (i == 3 ? 1.0f : 0.0f);
       k = 0;
       curve_sincos(tc, 0.0, phase, sn, cs);
+      uint8_t fl = (uint8_t)(a.flags[j] & kFlagNotSPD);
       if (a.reset_mult)
-        set_env_params(*a.nominal, a.reset_mult + c, a.E, false, a.params, a.derived, a.Ep, j);
+        fl = set_env_params(*a.nominal, a.reset_mult + c, a.E, false, a.params, a.derived, a.Ep,
+                            j) ? 0 : kFlagNotSPD;
+      a.flags[j] = fl;
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) a.state[i * a.Ep + j] = x[i];

@@ -61,8 +61,14 @@ struct ClassNominal {
   int32_t n_thr, lag;
 };
 
+// per-env status flags (internal [Ep] bytes): the state went non-finite in a
+// step (the env is then frozen), the mass matrix is not positive definite
+constexpr uint8_t kFlagNonFinite = 1;
+constexpr uint8_t kFlagNotSPD = 2;
+
 struct StepArgs {
   float* state;                // internal [D][Ep]
+  uint8_t* flags;              // internal [Ep] status flags (read, set when an env freezes)
   const float* derived;        // internal [kNumDerived][Ep]
   int64_t Ep;                  // internal row stride
   int64_t E;                   // caller row stride
@@ -81,6 +87,8 @@ struct StepArgs {
 
 struct ResetArgs {
   float* state;                // internal [D][Ep]
+  uint8_t* flags;              // internal [Ep]: kFlagNotSPD from the new parameters; the
+                               // non-finite flag cleared where the state is written
   float* params;               // internal [23][Ep] absolute
   float* derived;              // internal [kNumDerived][Ep]
   int64_t Ep, E;
@@ -109,6 +117,7 @@ struct TaskConst {
 
 struct TaskArgs {
   float* state;                // internal [D][Ep]
+  uint8_t* flags;              // internal [Ep]: cleared (kFlagNotSPD re-derived) on restart
   float* params;               // internal [23][Ep]
   float* derived;              // internal [kNumDerived][Ep]
   const float* task_f;         // internal [5][Ep]: centre x, y, z, curve phase, target yaw
@@ -240,6 +249,10 @@ hipError_t launch_reset(const ResetArgs& a, hipStream_t s);
 hipError_t launch_task(const ClassConst& cc, const TaskConst& tc, const TaskArgs& a, hipStream_t s);
 hipError_t launch_split(const ClassConst& cc, const SplitArgs& a, hipStream_t s);
 // out[r][perm[j]] = in[r][j] for rows r < rows (internal -> caller order)
+// status flags to caller order int32 [E]; flags &= mask for n envs
+hipError_t launch_flags_out(const uint8_t* flags, int32_t* out, int64_t E, const int32_t* perm,
+                            int64_t n_internal, hipStream_t s);
+hipError_t launch_flags_mask(uint8_t* flags, int64_t n, uint8_t mask, hipStream_t s);
 hipError_t launch_gather_out(const float* in, int64_t Ep, float* out, int64_t E, int32_t rows,
                              const int32_t* perm, int64_t n_internal, hipStream_t s);
 // out[r][j] = in[r][perm[j]] (caller -> internal order), padding lanes untouched

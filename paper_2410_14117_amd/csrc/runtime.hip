@@ -90,6 +90,7 @@ struct mg_sim {
   int32_t* perm = nullptr;     // [Ep] internal -> caller (-1 for padding), NULL = identity
   int32_t* iperm = nullptr;    // [E] caller -> internal, NULL = identity
   uint8_t* class_of = nullptr; // [Ep]
+  uint8_t* flags = nullptr;    // [Ep] status flags (kFlagNonFinite, kFlagNotSPD)
   ClassNominal* nominal_dev = nullptr;
   double* partials = nullptr;
   size_t partials_cap = 0;     // doubles
@@ -260,6 +261,7 @@ mg_status enqueue_steps(mg_sim* s, hipStream_t st, const float* actions, int32_t
   StepArgs a;
   std::memset(&a, 0, sizeof(a));
   a.state = s->state;
+  a.flags = s->flags;
   a.derived = s->derived;
   a.Ep = s->Ep;
   a.E = s->E;
@@ -316,6 +318,7 @@ mg_status reset_impl(mg_sim* s, const int64_t* ids, int64_t n, const float* stat
   ResetArgs r;
   std::memset(&r, 0, sizeof(r));
   r.state = s->state;
+  r.flags = s->flags;
   r.params = s->params;
   r.derived = s->derived;
   r.Ep = s->Ep;
@@ -435,6 +438,7 @@ mg_status enqueue_task(mg_sim* s, const float* actions, float* obs, float* err, 
   TaskArgs a;
   std::memset(&a, 0, sizeof(a));
   a.state = s->state;
+  a.flags = s->flags;
   a.params = s->params;
   a.derived = s->derived;
   a.task_f = s->task_f;
@@ -483,6 +487,7 @@ const char* mg_status_str(mg_status s) {
     case MG_ERR_DEVICE: return "device error";
     case MG_ERR_UNSUPPORTED: return "unsupported";
     case MG_ERR_BUSY: return "busy";
+    case MG_ERR_CANCELLED: return "cancelled";
     default: return "unknown status";
   }
 }
@@ -593,7 +598,7 @@ mg_status mg_create(const mg_config* cfg, mg_sim** out) {
   if (hipMalloc(&s->state, Ep * s->D * sizeof(float)) != hipSuccess ||
       hipMalloc(&s->params, Ep * kNumParams * sizeof(float)) != hipSuccess ||
       hipMalloc(&s->derived, Ep * kNumDerived * sizeof(float)) != hipSuccess ||
-      hipMalloc(&s->class_of, Ep) != hipSuccess ||
+      hipMalloc(&s->class_of, Ep) != hipSuccess || hipMalloc(&s->flags, Ep) != hipSuccess ||
       hipMalloc(&s->nominal_dev, sizeof(ClassNominal) * s->n_classes) != hipSuccess ||
       hipMalloc(&s->staging, (size_t)E * std::max(s->D, kNumParams) * sizeof(float)) != hipSuccess ||
       (!identity && (hipMalloc(&s->perm, Ep * sizeof(int32_t)) != hipSuccess ||
@@ -605,6 +610,7 @@ mg_status mg_create(const mg_config* cfg, mg_sim** out) {
       hipMemset(s->state, 0, Ep * s->D * sizeof(float)) != hipSuccess ||
       hipMemset(s->params, 0, Ep * kNumParams * sizeof(float)) != hipSuccess ||
       hipMemset(s->derived, 0, Ep * kNumDerived * sizeof(float)) != hipSuccess ||
+      hipMemset(s->flags, 0, Ep) != hipSuccess ||
       hipMemcpy(s->class_of, cls.data(), Ep, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(s->nominal_dev, s->nominal.data(), sizeof(ClassNominal) * s->n_classes,
                 hipMemcpyHostToDevice) != hipSuccess ||
@@ -652,7 +658,7 @@ void mg_destroy(mg_sim* s) {
     for (hipStream_t h : s->aux) (void)hipStreamDestroy(h);
     for (hipEvent_t e : s->ev_fork) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->ev_join) (void)hipEventDestroy(e);
-    void* bufs[] = {s->state, s->params, s->derived, s->perm, s->iperm, s->class_of,
+    void* bufs[] = {s->state, s->params, s->derived, s->perm, s->iperm, s->class_of, s->flags,
                     s->nominal_dev, s->partials, s->staging, s->segbuf, s->task_f, s->task_k,
                     s->split_acc};
     for (void* b : bufs)
@@ -705,6 +711,23 @@ mg_status mg_set_state(mg_sim* s, const float* state) {
                                s->E * sizeof(float), s->D, hipMemcpyDeviceToDevice, s->stream));
   } else {
     MG_HIP(s, launch_scatter_in(state, s->E, s->state, s->Ep, s->D, s->perm, s->Ep, s->stream));
+  }
+  // new states: no env is frozen for its state any more
+  MG_HIP(s, launch_flags_mask(s->flags, s->Ep, (uint8_t)~kFlagNonFinite, s->stream));
+  return MG_OK;
+}
+
+mg_status mg_get_flags(mg_sim* s, int32_t* out, int32_t out_on_device) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!out) return fail(s, MG_ERR_INVALID, "out is NULL");
+  DeviceGuard g(s->device);
+  int32_t* dst = out_on_device ? out : reinterpret_cast<int32_t*>(s->staging);
+  MG_HIP(s, launch_flags_out(s->flags, dst, s->E, s->perm, s->Ep, s->stream));
+  if (!out_on_device) {
+    MG_HIP(s, hipMemcpyAsync(out, s->staging, (size_t)s->E * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s->stream));
+    MG_HIP(s, hipStreamSynchronize(s->stream));
   }
   return MG_OK;
 }

@@ -74,6 +74,12 @@ class TicketBook {
     if (latency_s) *latency_s = (double)(r.done - r.arrival) * 1e-9;
     return r.status;
   }
+  // Whether the ticket was issued and has not completed yet.
+  bool open_ticket(uint64_t ticket) const {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = rec_.find(ticket);
+    return it != rec_.end() && !it->second.finished;
+  }
   // Tickets issued and not yet consumed.
   size_t size() const {
     std::lock_guard<std::mutex> lk(mu_);
@@ -161,6 +167,19 @@ class AdmissionQueue {
     std::lock_guard<std::mutex> lk(mu_);
     return err_;
   }
+  // Removes the first queued request for which match(r) holds and returns it
+  // (the caller completes it), or NULL.
+  template <class Match>
+  T* remove_first(Match&& match) {
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto it = q_.begin(); it != q_.end(); ++it)
+      if (match(*it)) {
+        T* r = *it;
+        q_.erase(it);
+        return r;
+      }
+    return nullptr;
+  }
   // Removes and returns every queued request (the caller completes them).
   std::deque<T*> take_all() {
     std::lock_guard<std::mutex> lk(mu_);
@@ -202,24 +221,24 @@ class DeliveryQueue {
   using Piece = DeliveryPiece<Req, Group>;
 
   // Cuts the results of one group's requests into pieces of at most `chunk`
-  // floats and queues them.  Each entry of reqs is (request, its output, its
-  // length in floats); their results lie back to back from `base`.
-  void post(Group* group, const float* base,
-            const std::vector<std::tuple<Req*, float*, size_t>>& reqs, size_t chunk) {
+  // floats and queues them.  Each entry of reqs is (request, where its result
+  // lies in the group's buffer, its output, its length in floats).
+  void post(Group* group,
+            const std::vector<std::tuple<Req*, const float*, float*, size_t>>& reqs,
+            size_t chunk) {
     int pieces = 0;
-    for (auto& r : reqs) pieces += (int)((std::get<2>(r) + chunk - 1) / chunk);
+    for (auto& r : reqs) pieces += (int)((std::get<3>(r) + chunk - 1) / chunk);
     auto pg = std::make_shared<std::atomic<int>>(pieces);
     {
       std::lock_guard<std::mutex> lk(mu_);
-      size_t o = 0;
       for (auto& r : reqs) {
-        const size_t len = std::get<2>(r);
+        const size_t len = std::get<3>(r);
         auto pr = std::make_shared<std::atomic<int>>((int)((len + chunk - 1) / chunk));
         for (size_t b = 0; b < len; b += chunk) {
           Piece p;
           p.req = std::get<0>(r);
-          p.src = base + o;
-          p.dst = std::get<1>(r);
+          p.src = std::get<1>(r);
+          p.dst = std::get<2>(r);
           p.begin = b;
           p.end = b + chunk < len ? b + chunk : len;
           p.group = group;
@@ -227,7 +246,6 @@ class DeliveryQueue {
           p.pending_group = pg;
           q_.push_back(std::move(p));
         }
-        o += len;
       }
     }
     cv_.notify_all();

@@ -34,6 +34,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <utility>
 #include <vector>
 
@@ -67,6 +68,7 @@ struct Request {
   std::vector<int32_t> cols;         // [pages][64]
   std::vector<int32_t> entry;        // per page: its entry in the class's tick list
   int64_t t0 = 0;                    // tick of its first control step
+  bool cancelled = false;            // retired without delivery (mg_server_cancel)
 };
 
 // Pinned host buffer mapped into the device's address space: the host writes
@@ -221,6 +223,10 @@ struct mg_server {
   std::mutex err_mu;
   std::string err;                 // first failure, kept for mg_server_last_error
   int64_t fail_tick = 0;           // test hook: treat this tick's completion as failed
+  // tickets of admitted requests to cancel at the next tick
+  std::mutex cancel_mu;
+  std::unordered_set<uint64_t> cancels;
+  std::atomic<int64_t> n_cancels{0};
   std::thread thr;
   // delivery threads: copy finished requests' states to the clients, free their
   // pages and complete them, off the scheduler thread; a few of them, so that a
@@ -275,6 +281,10 @@ ClassNominal class_nominal(const mg_vehicle& v) {
 
 void finish(mg_server* S, Request* r, mg_status st) {
   if (st == MG_OK) S->completed.fetch_add(1);
+  if (S->n_cancels.load() > 0) {
+    std::lock_guard<std::mutex> lk(S->cancel_mu);
+    if (S->cancels.erase(r->ticket)) S->n_cancels.store((int64_t)S->cancels.size());
+  }
   S->book.close(r->ticket, st, clock_ns());
   delete r;
 }
@@ -388,6 +398,18 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
                              S->stream));
     for (Request* r : admitted) S->active.push_back(r);
     admitted.clear();
+  }
+
+  // cancelled requests retire this tick, without delivery (their pages still
+  // run this tick's launch, to no effect on any other page)
+  if (S->n_cancels.load() > 0) {
+    std::lock_guard<std::mutex> lk(S->cancel_mu);
+    for (Request* r : S->active)
+      if (S->cancels.erase(r->ticket)) {
+        r->cancelled = true;
+        r->step = r->L;
+      }
+    S->n_cancels.store((int64_t)S->cancels.size());
   }
 
   // 2. the tick itself: every page advances min(K, steps its request has left);
@@ -507,10 +529,31 @@ bool retire_oldest(mg_server* S, bool block, bool* took) {
   if (e != hipSuccess) return fail_server(S, std::string("tick: ") + hipGetErrorString(e));
   S->inflight.pop_front();
   if (!sl.retiring.empty()) {
-    std::vector<std::tuple<Request*, float*, size_t>> reqs;
+    std::vector<std::tuple<Request*, const float*, float*, size_t>> reqs;
+    std::vector<Request*> cancelled;
     reqs.reserve(sl.retiring.size());
-    for (Request* r : sl.retiring) reqs.emplace_back(r, r->out, (size_t)r->n * S->D);
-    S->deliveries.post(sl.out, sl.out->h, reqs, mg_server::kDeliverChunk);
+    size_t o = 0;
+    for (Request* r : sl.retiring) {
+      const size_t len = (size_t)r->n * S->D;
+      if (r->cancelled)
+        cancelled.push_back(r);
+      else
+        reqs.emplace_back(r, sl.out->h + o, r->out, len);
+      o += len;
+    }
+    for (Request* r : cancelled) {
+      {
+        std::lock_guard<std::mutex> lk(S->pool_mu);
+        S->pool->release(r->pages);
+      }
+      finish(S, r, MG_ERR_CANCELLED);
+    }
+    if (!reqs.empty()) {
+      S->deliveries.post(sl.out, reqs, mg_server::kDeliverChunk);
+    } else {
+      std::lock_guard<std::mutex> lk(S->dmu);
+      S->out_pool.push_back(sl.out);
+    }
     sl.retiring.clear();
     sl.out = nullptr;
   }
@@ -853,6 +896,29 @@ mg_status mg_server_submit(mg_server* S, const mg_request* req, uint64_t* ticket
   if (st != MG_OK) return st;
   r.release();
   *ticket = raw->ticket;
+  return MG_OK;
+}
+
+mg_status mg_server_cancel(mg_server* S, uint64_t ticket) {
+  if (!S || !S->book.open_ticket(ticket)) return MG_ERR_INVALID;
+  Request* r = S->queue->remove_first([&](Request* q) { return q->ticket == ticket; });
+  if (r) {
+    S->queued.fetch_sub(1);
+    finish(S, r, MG_ERR_CANCELLED);
+    return MG_OK;
+  }
+  // admitted (or about to be): the scheduler retires it at its next tick
+  {
+    std::lock_guard<std::mutex> lk(S->cancel_mu);
+    S->cancels.insert(ticket);
+    S->n_cancels.store((int64_t)S->cancels.size());
+  }
+  // it may have completed meanwhile: then the entry is dropped here
+  if (!S->book.open_ticket(ticket)) {
+    std::lock_guard<std::mutex> lk(S->cancel_mu);
+    S->cancels.erase(ticket);
+    S->n_cancels.store((int64_t)S->cancels.size());
+  }
   return MG_OK;
 }
 

@@ -18,7 +18,8 @@ NUM_PARAMS = 23
 NUM_THETA = 19
 NUM_STATS = 4
 
-MG_OK, MG_ERR_INVALID, MG_ERR_OOM, MG_ERR_DEVICE, MG_ERR_UNSUPPORTED, MG_ERR_BUSY = range(6)
+(MG_OK, MG_ERR_INVALID, MG_ERR_OOM, MG_ERR_DEVICE, MG_ERR_UNSUPPORTED, MG_ERR_BUSY,
+ MG_ERR_CANCELLED) = range(7)
 
 
 class MgError(RuntimeError):
@@ -127,6 +128,7 @@ _SIGS = {
     "mg_get_state": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
     "mg_get_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
     "mg_synchronize": (ctypes.c_int32, [_vp]),
+    "mg_get_flags": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
     "mg_clock_ns": (ctypes.c_uint64, []),
     "mg_server_create": (ctypes.c_int32, [ctypes.POINTER(MgServerConfig), ctypes.POINTER(_vp)]),
     "mg_server_submit": (ctypes.c_int32, [_vp, ctypes.POINTER(MgRequest),
@@ -134,6 +136,7 @@ _SIGS = {
     "mg_server_wait": (ctypes.c_int32, [_vp, ctypes.c_uint64, ctypes.c_int64,
                                         ctypes.POINTER(ctypes.c_double)]),
     "mg_server_get_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(MgServerStats)]),
+    "mg_server_cancel": (ctypes.c_int32, [_vp, ctypes.c_uint64]),
     "mg_server_last_error": (ctypes.c_char_p, [_vp]),
     "mg_server_destroy": (None, [_vp]),
     "mg_step_split": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp]),
@@ -427,6 +430,15 @@ class Sim:
     def synchronize(self):
         self._check(lib().mg_synchronize(self._h))
 
+    def get_flags(self):
+        """Per-env status flags (int32 [E] device tensor): 1 = state went non-finite, 2 = mass
+        matrix not positive definite; a flagged env is frozen."""
+        import torch
+        out = torch.empty((self.n_envs,), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._bind_stream()
+        self._check(lib().mg_get_flags(self._h, out.data_ptr(), 1))
+        return out
+
     # -- adjoint ---------------------------------------------------------------------------
     def adj_forward(self, actions, ckpt_every, ckpt=None, traj=None):
         """Rollout of T = actions.shape[0] control steps from the current state, saving a
@@ -562,13 +574,14 @@ class Server:
                 self._keep.pop(ticket, None)
         return st, lat.value
 
-    def replay(self, requests, t0_ns, n_clients):
+    def replay(self, requests, n_clients, start_delay_ns=20_000_000):
         """Replays an arrival trace from n_clients native client threads (libmg_clients.so,
         mgc_replay): request i is submitted by client requests[i]["client"] at
-        t0_ns + requests[i]["at_ns"], stamped with that arrival, and waited for by the same
-        thread.  Each request is a dict with client, at_ns, n_envs, n_steps, x0_ptr, ld, out
-        (host [D][n_envs] float32), and optionally env_class, mult_ptr, actions_ptr or
-        action_seed.  Returns (status [n] int32, latency_s [n], submit lag ns [n])."""
+        t0 + requests[i]["at_ns"], stamped with that arrival, and waited for by the same
+        thread; t0 is start_delay_ns after the requests have been marshalled.  Each request
+        is a dict with client, at_ns, n_envs, n_steps, x0_ptr, ld, out (host [D][n_envs]
+        float32), and optionally env_class, mult_ptr, actions_ptr or action_seed.  Returns
+        (status [n] int32, latency_s [n], submit lag ns [n], t0 on mg_clock_ns)."""
         n = len(requests)
         reqs = (MgRequest * max(1, n))()
         client = np.zeros(max(1, n), np.int32)
@@ -601,12 +614,17 @@ class Server:
         status = np.zeros(max(1, n), np.int32)
         lat = np.zeros(max(1, n), np.float64)
         lag = np.zeros(max(1, n), np.int64)
-        rc = clients_lib().mgc_replay(self._h, int(n_clients), n, client.ctypes.data,
-                                      at.ctypes.data, reqs, int(t0_ns), status.ctypes.data,
-                                      lat.ctypes.data, lag.ctypes.data)
+        L = clients_lib()
+        t0 = int(Server.clock_ns()) + int(start_delay_ns)
+        rc = L.mgc_replay(self._h, int(n_clients), n, client.ctypes.data, at.ctypes.data, reqs,
+                          t0, status.ctypes.data, lat.ctypes.data, lag.ctypes.data)
         if rc != 0:
             raise ValueError("mgc_replay rejected its arguments")
-        return status[:n], lat[:n], lag[:n]
+        return status[:n], lat[:n], lag[:n], t0
+
+    def cancel(self, ticket):
+        """Cancels a request that has not completed (mg_server_cancel); returns the status."""
+        return lib().mg_server_cancel(self._h, int(ticket))
 
     def last_error(self):
         return (lib().mg_server_last_error(self._h) or b"").decode()

@@ -1,12 +1,13 @@
 // CPU run of the FP32 adjoint backward's source (fossen_adjoint.h): the
 // per-env backward adj_bwd_env, host and device code, is run on the host for
-// every env of small rollouts, in three forms that must agree bitwise:
+// every env of small rollouts, in four forms that must agree bitwise:
 //   current   the backward that recomputes each segment with its own loop
 //   factored  the same with that loop replaced by a call of recompute_segment
 //             (the form that once gave wrong gradients on the GPU for the
 //             one-wave 8-thruster lag kernel)
 //   whole     every segment recomputed first by recompute_segment into a
 //             whole-rollout buffer, then the sweep-only backward
+//   prefetch  the sweep that loads each next sub-step's inputs one step ahead
 // Built with AddressSanitizer and UndefinedBehaviorSanitizer for the host, so
 // that an out-of-bounds access or undefined operation in that source is
 // reported.  No kernel is launched.  Prints "N failures".
@@ -212,6 +213,8 @@ void check(unsigned seed, int E, int T, int K, int S, int map, float dt) {
       const HalfInvT<float> A = half_step_inverse(Ps[e], sc.h2);
       if (form == 0) {
         adj_bwd_env<N, LAG, false>(a, cc, Ps[e], sc, A, e, e);
+      } else if (form == 3) {
+        adj_bwd_env<N, LAG, false, true>(a, cc, Ps[e], sc, A, e, e);
       } else if (form == 1) {
         adj_bwd_env_factored<N, LAG>(a, cc, Ps[e], sc, A, e, e);
       } else {
@@ -226,7 +229,7 @@ void check(unsigned seed, int E, int T, int K, int S, int map, float dt) {
     }
     return o;
   };
-  const Out cur = run(0), fac = run(1), whole = run(2);
+  const Out cur = run(0), fac = run(1), whole = run(2), pre = run(3);
   auto same = [](const std::vector<float>& x, const std::vector<float>& y) {
     return x.size() == y.size() && std::memcmp(x.data(), y.data(), x.size() * 4) == 0;
   };
@@ -237,10 +240,12 @@ void check(unsigned seed, int E, int T, int K, int S, int map, float dt) {
   };
   const bool ok = same(cur.gact, fac.gact) && same(cur.gth, fac.gth) && same(cur.gx0, fac.gx0) &&
                   same(cur.gact, whole.gact) && same(cur.gth, whole.gth) &&
-                  same(cur.gx0, whole.gx0) && finite(cur.gact) && finite(cur.gth) &&
+                  same(cur.gx0, whole.gx0) && same(cur.gact, pre.gact) &&
+                  same(cur.gth, pre.gth) && same(cur.gx0, pre.gx0) && finite(cur.gact) &&
+                  finite(cur.gth) &&
                   finite(cur.gx0);
   std::printf("N=%d lag=%d E=%d T=%d K=%d S=%d: %s\n", N, (int)LAG, E, T, K, S,
-              ok ? "current = factored = whole, bitwise, all finite" : "MISMATCH");
+              ok ? "current = factored = whole = prefetching, bitwise, all finite" : "MISMATCH");
   if (!ok) ++failures;
 }
 

@@ -131,14 +131,14 @@ struct Server {
       size_t total = 0;
       for (Req* r : taken) total += r->len;
       g->data.resize(total);
-      std::vector<std::tuple<Req*, float*, size_t>> reqs;
+      std::vector<std::tuple<Req*, const float*, float*, size_t>> reqs;
       size_t o = 0;
       for (Req* r : taken) {
         for (size_t i = 0; i < r->len; ++i) g->data[o + i] = value(r->ticket, i);
-        reqs.emplace_back(r, r->out, r->len);
+        reqs.emplace_back(r, g->data.data() + o, r->out, r->len);
         o += r->len;
       }
-      deliveries.post(g, g->data.data(), reqs, kChunk);
+      deliveries.post(g, reqs, kChunk);
     }
     const mg_status st = queue.failed() ? MG_ERR_DEVICE : MG_ERR_BUSY;
     for (Req* r : queue.take_all()) finish(r, st);
@@ -277,9 +277,11 @@ void single_thread_cases() {
   TicketBook b;
   const uint64_t t = b.open(100);
   double lat = -1;
+  CHECK(b.open_ticket(t) && !b.open_ticket(t + 1));
   CHECK(b.wait(t, 1000, &lat) == MG_ERR_BUSY);          // not completed: times out
   CHECK(b.wait(t + 1, 0, &lat) == MG_ERR_INVALID);      // never issued
   b.close(t, MG_OK, 600);
+  CHECK(!b.open_ticket(t));
   b.close(t, MG_ERR_DEVICE, 900);                       // a second close is ignored
   CHECK(b.wait(t, -1, &lat) == MG_OK && std::fabs(lat - 500e-9) < 1e-15);
   CHECK(b.wait(t, -1, &lat) == MG_ERR_INVALID);         // consumed
@@ -289,6 +291,9 @@ void single_thread_cases() {
   auto none = [](Req*) {};
   CHECK(q.push(&a, none) == MG_OK && q.push(&c, none) == MG_OK);
   CHECK(q.push(&d, none) == MG_ERR_BUSY);               // full
+  CHECK(q.remove_first([&](Req* r) { return r == &c; }) == &c && q.size() == 1);
+  CHECK(q.remove_first([&](Req* r) { return r == &c; }) == nullptr);
+  CHECK(q.push(&c, none) == MG_OK && q.size() == 2);
   std::vector<Req*> taken, dropped;
   int seen = 0;
   q.admit([&](Req*) { return ++seen == 1 ? AdmissionQueue<Req>::Admit::Take

@@ -39,7 +39,7 @@ def test_client_driver_exports_every_declared_symbol():
 def test_abi_version_and_status_strings():
     L = mg.lib()
     assert L.mg_abi_version() == mg.MG_ABI_VERSION
-    for s in range(6):
+    for s in range(7):
         assert L.mg_status_str(s)
     assert L.mg_status_str(99) == b"unknown status"
 

@@ -1,9 +1,9 @@
 """CPU run of the FP32 adjoint backward's own source (fossen_adjoint.h: adj_bwd_env and
 recompute_segment, host and device code): tests/adj_host_check.hip runs the backward of
 every env of small rollouts (8 thrusters with and without lag, 6 with and without, 1 with
-lag; one and several segments) in three forms -- its own recomputation loop, that loop
-factored into recompute_segment, and the whole-rollout recomputation then the sweep --
-which must agree bitwise, built for the host with AddressSanitizer and
+lag; one and several segments) in four forms -- its own recomputation loop, that loop
+factored into recompute_segment, the whole-rollout recomputation then the sweep, and the
+sweep that loads each next sub-step's inputs one step ahead -- which must agree bitwise, built for the host with AddressSanitizer and
 UndefinedBehaviorSanitizer (GPU code is not instrumented)."""
 import os
 import shutil

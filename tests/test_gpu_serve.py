@@ -467,7 +467,7 @@ def test_native_clients_replay(mgmod, pools):
                          "action_seed": int(rng.integers(0, 2 ** 63)), "off": off})
     srv = mgmod.Server(CLASSES, DT, S, steps_per_tick=8)
     say(f"serve native replay: {len(reqs)} requests from 32 client threads")
-    status, lat, lag = srv.replay(reqs, mgmod.Server.clock_ns() + 20_000_000, 32)
+    status, lat, lag, _ = srv.replay(reqs, 32)
     assert (status == 0).all() and (lat > 0).all()
     for q in reqs:
         assert np.isfinite(q["out"]).all()
@@ -529,3 +529,48 @@ def test_reserved_staging_defers_instead_of_growing(mgmod):
         assert ref.wait(tk, 60_000_000)[0] == 0
         np.testing.assert_array_equal(out, subs[k][1])
     ref.close()
+
+
+def test_cancel_queued_and_admitted_requests(mgmod, pools):
+    """A server capped at A's pages plus 10 (256 sub-steps per control step, one control
+    step per tick): A (40 000 envs x 64 steps) is admitted, B (2000 envs) waits for pages
+    and C (300 envs) waits behind B (FIFO admission).  Cancelling C takes it out of the
+    queue at once; cancelling A retires it at the next tick without delivery (its output
+    stays as the client left it); both complete with MG_ERR_CANCELLED.  B then runs on the
+    freed pages and its result equals, bitwise, B served alone.  A completed ticket cannot
+    be cancelled."""
+    from paper_2410_14117_amd.mg import MG_ERR_CANCELLED, MG_ERR_INVALID
+    page = mgmod.page_bytes(D)
+    c = pools["cls"][:40000]
+    pages_a = -(-int((c == 0).sum()) // 64) - (-int((c == 1).sum()) // 64)
+    S256, dt = 256, DT / 64
+    srv = mgmod.Server(CLASSES, dt, S256, mem_cap_bytes=(pages_a + 10) * page)
+    outs = {k: np.full((D, n), -7.0, np.float32) for k, n in (("A", 40000), ("B", 2000),
+                                                               ("C", 300))}
+    say("serve cancel: A admitted, B and C queued")
+    st, ta = srv.submit(out=outs["A"], **_req(pools, 0, 40000, 64))
+    assert st == 0
+    t0 = time.time()
+    while srv.stats()["active_envs"] == 0 and time.time() - t0 < 30:
+        pass
+    st, tb = srv.submit(out=outs["B"], **_req(pools, 100, 2000, 5))
+    assert st == 0
+    st, tc = srv.submit(out=outs["C"], **_req(pools, 5000, 300, 5))
+    assert st == 0
+    assert srv.stats()["queued"] == 2
+    assert srv.cancel(tc) == 0
+    assert srv.cancel(ta) == 0
+    assert srv.wait(tc, 60_000_000)[0] == MG_ERR_CANCELLED
+    assert srv.wait(ta, 60_000_000)[0] == MG_ERR_CANCELLED
+    assert srv.wait(tb, 60_000_000)[0] == 0
+    assert (outs["A"] == -7.0).all() and (outs["C"] == -7.0).all()
+    assert srv.cancel(tb) == MG_ERR_INVALID and srv.cancel(12345678) == MG_ERR_INVALID
+    st = srv.stats()
+    assert st["queued"] == 0 and st["completed"] == 1
+    srv.close()
+    ref = mgmod.Server(CLASSES, dt, S256)
+    alone = np.zeros((D, 2000), np.float32)
+    st, t = ref.submit(out=alone, **_req(pools, 100, 2000, 5))
+    assert st == 0 and ref.wait(t, 60_000_000)[0] == 0
+    ref.close()
+    np.testing.assert_array_equal(outs["B"], alone)

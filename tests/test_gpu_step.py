@@ -211,7 +211,17 @@ def test_reset_subset_params_and_resume(mgmod):
     sim2.close()
 
 
-def test_nonfinite_env_is_counted_and_isolated(mgmod):
+@pytest.mark.parametrize("mode", ["fused", "graph"])
+def test_nonfinite_env_is_frozen_flagged_and_counted(mgmod, mode):
+    """Env 200's mass multiplier is -2 (M not positive definite): mg_reset flags it
+    MG_FLAG_NOT_SPD and it is never stepped: its initial state throughout.  Env 100 gets a
+    NaN throttle at control step 3: its state goes non-finite there and, at the end of that
+    launch, goes back to the launch's input and is flagged MG_FLAG_NONFINITE -- with the 12
+    control steps in one launch (fused) to x0, with one launch per control step (graph
+    rollout) to its last finite state, which later launches keep.  Every other env equals,
+    bitwise, the same run without the NaN; the statistics count the frozen and non-finite
+    envs; mg_set_state clears the non-finite flag and a reset with valid multipliers clears
+    the other."""
     E, T = 512, 12
     v = LAGGED["heavy"]
     x0 = initial_state(E, 21, 81)
@@ -220,14 +230,44 @@ def test_nonfinite_env_is_counted_and_isolated(mgmod):
     bad[3, 1, 100] = np.nan
     mult = param_multipliers(E, 0.2, 83)
     mult[0, 200] = -2.0                  # mass -23 kg: M not positive definite
-    say("non-finite")
-    tr_ok, st_ok, _ = _run(mgmod, v, x0, act, 0.005, 4, mult=mult)
-    tr_bad, st_bad, _ = _run(mgmod, v, x0, bad, 0.005, 4, mult=mult)
-    assert np.all(np.isnan(tr_ok[:, :, 200]).any(axis=1))
+
+    def run(a):
+        sim = mgmod.Sim(v, E, 0.005, 4)
+        sim.reset(state=dev(x0), param_mult=dev(mult))
+        traj = torch.empty((T, 21, E), dtype=torch.float32, device="cuda")
+        stats = torch.empty((T, 4), dtype=torch.float64, device="cuda")
+        if mode == "fused":
+            sim.step(dev(a), traj=traj, stats=stats)
+        else:
+            sim.rollout(dev(a), traj=traj, stats=stats)
+        return sim, host(traj), host(stats), host(sim.get_flags())
+
+    say(f"non-finite, {mode}")
+    sim_ok, tr_ok, st_ok, fl_ok = run(act)
+    sim_bad, tr_bad, st_bad, fl_bad = run(bad)
+    assert fl_ok[200] == 2 and fl_bad[200] == 2 and fl_bad[100] == 1
+    assert np.count_nonzero(fl_ok) == 1 and np.count_nonzero(fl_bad) == 2
+    for t in range(T):
+        np.testing.assert_array_equal(tr_ok[t, :, 200], x0[:, 200])
+    np.testing.assert_array_equal(tr_bad[:3, :, 100], tr_ok[:3, :, 100])
+    assert not np.isfinite(tr_bad[3, :, 100]).all()
+    if mode == "fused":
+        np.testing.assert_array_equal(host(sim_bad.get_state())[:, 100], x0[:, 100])
+    else:
+        for t in range(4, T):
+            np.testing.assert_array_equal(tr_bad[t, :, 100], tr_bad[2, :, 100])
+        np.testing.assert_array_equal(host(sim_bad.get_state())[:, 100], tr_bad[2, :, 100])
     assert np.all(st_ok[:, 3] == 1)
     assert list(st_bad[:, 3]) == [1, 1, 1] + [2] * (T - 3)
     keep = np.setdiff1d(np.arange(E), [100])
     np.testing.assert_array_equal(tr_bad[:, :, keep], tr_ok[:, :, keep])
+    # a new state clears the non-finite flag, valid multipliers the other
+    sim_bad.set_state(dev(x0))
+    assert list(np.flatnonzero(host(sim_bad.get_flags()))) == [200]
+    sim_bad.reset(state=dev(x0), param_mult=dev(param_multipliers(E, 0.2, 83)))
+    assert np.count_nonzero(host(sim_bad.get_flags())) == 0
+    sim_ok.close()
+    sim_bad.close()
 
 
 def test_heave_steady_state_on_gpu(mgmod):

@@ -646,6 +646,58 @@ def summarise_profile(root):
     return "\n".join(out)
 
 
+def traffic_from_counters(root):
+    """The content of profiles/traffic.json from the FETCH_SIZE and WRITE_SIZE --pmc runs
+    under root (pmc_fetch/, pmc_write/; bench.py run with --calib-copy): per-dispatch means
+    (KiB) of the fused and, when present, plain step launches of each class, scaled by what
+    each counter reads for the 1 GiB device copy, in bytes; host-only."""
+    import csv
+    import collections
+    import glob
+
+    def load(sub, counter):
+        vals = collections.defaultdict(list)
+        for f in glob.glob(os.path.join(root, sub, "**", "*counter_collection.csv"),
+                           recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return vals
+
+    fetch, write = load("pmc_fetch", "FETCH_SIZE"), load("pmc_write", "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    ff = gib_kib / max(fetch["__amd_rocclr_copyBuffer"])
+    fw = gib_kib / max(write["__amd_rocclr_copyBuffer"])
+
+    def per_launch(n, plain):
+        k = f"void mg::k_step<{n}, true, {'true' if plain else 'false'}>(mg::StepArgs, mg::ClassConst)"
+        if k not in fetch or k not in write:
+            return None
+        return 1024.0 * (ff * sum(fetch[k]) / len(fetch[k]) + fw * sum(write[k]) / len(write[k]))
+
+    out = {"source_hash": kernel_source_hash(),
+           "what": "HBM bytes from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE runs (KiB "
+                   "per dispatch, mean over the dispatches of each class), each scaled by what "
+                   f"the same counter reads for a 1 GiB device copy (FETCH x{ff:.6f}, WRITE "
+                   f"x{fw:.6f}); fused: both class launches of one control step (524,288 "
+                   "BlueROV2 + 524,288 Heavy envs, 16 RK4 sub-steps); plain: both class "
+                   "launches of one sub-step",
+           "per_launch": {}, "fetch_factor": ff, "write_factor": fw}
+    for label, n, plain in (("fused_bluerov2", 6, False), ("fused_heavy", 8, False),
+                            ("plain_bluerov2", 6, True), ("plain_heavy", 8, True)):
+        v = per_launch(n, plain)
+        if v is not None:
+            out["per_launch"][label] = v
+    pl = out["per_launch"]
+    if "fused_bluerov2" in pl and "fused_heavy" in pl:
+        out["k_step_fused_control_step"] = pl["fused_bluerov2"] + pl["fused_heavy"]
+    if "plain_bluerov2" in pl and "plain_heavy" in pl:
+        out["k_step_plain_substep"] = pl["plain_bluerov2"] + pl["plain_heavy"]
+    out["algorithmic_fused_control_step"] = (524288 * fused_algo_bytes(6, True) +
+                                             524288 * fused_algo_bytes(8, True))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -670,9 +722,18 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE calibrate the counters of a --pmc run")
     ap.add_argument("--summarise-profile", metavar="DIR",
                     help="print a summary of the rocprofv3 CSV files under DIR and exit")
+    ap.add_argument("--traffic-from", metavar="DIR",
+                    help="write profiles/traffic.json from the FETCH_SIZE / WRITE_SIZE runs "
+                         "under DIR (pmc_fetch/, pmc_write/) and exit")
     args = ap.parse_args()
     if args.summarise_profile:
         print(summarise_profile(args.summarise_profile))
+        return
+    if args.traffic_from:
+        t = traffic_from_counters(args.traffic_from)
+        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+            json.dump(t, f, indent=1)
+        print(json.dumps(t))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the environments are independent and this "

@@ -90,3 +90,32 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_traffic_from_counters(tmp_path):
+    """traffic.json from synthetic FETCH_SIZE / WRITE_SIZE CSVs: the copy of 1 GiB that reads
+    half its bytes in FETCH_SIZE calibrates fetches by 2, writes by 1; per launch the means,
+    in bytes; the control step sums the two classes' fused launches."""
+    rows = {"pmc_fetch": ("FETCH_SIZE", {"__amd_rocclr_copyBuffer": [524288.0, 4.0],
+                                         "void mg::k_step<6, true, false>(mg::StepArgs, mg::ClassConst)": [1000.0, 1200.0],
+                                         "void mg::k_step<8, true, false>(mg::StepArgs, mg::ClassConst)": [2000.0]}),
+            "pmc_write": ("WRITE_SIZE", {"__amd_rocclr_copyBuffer": [1048576.0],
+                                         "void mg::k_step<6, true, false>(mg::StepArgs, mg::ClassConst)": [300.0, 500.0],
+                                         "void mg::k_step<8, true, false>(mg::StepArgs, mg::ClassConst)": [700.0]})}
+    for sub, (counter, kern) in rows.items():
+        d = tmp_path / sub / "run"
+        d.mkdir(parents=True)
+        with open(d / "x_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, ["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for k, vals in kern.items():
+                for v in vals:
+                    w.writerow({"Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
+    t = bench.traffic_from_counters(str(tmp_path))
+    assert t["fetch_factor"] == 2.0 and t["write_factor"] == 1.0
+    assert t["per_launch"]["fused_bluerov2"] == 1024.0 * (2 * 1100.0 + 400.0)
+    assert t["per_launch"]["fused_heavy"] == 1024.0 * (2 * 2000.0 + 700.0)
+    assert t["k_step_fused_control_step"] == 1024.0 * (2600.0 + 4700.0)
+    assert "k_step_plain_substep" not in t
+    assert t["source_hash"] == bench.kernel_source_hash()
+    assert t["algorithmic_fused_control_step"] == 524288 * (268 + 292)

@@ -217,7 +217,9 @@ def cpu_other_workloads(threads):
 
 def bench_adjoint(torch, mg, reps=5, n_envs=None):
     """C4: 8192 BlueROV2 envs, 64 control steps of 10 ms, checkpoint every 8; forward with
-    checkpoints, backward (recompute + reverse sweep), against the plain per-step launch."""
+    checkpoints and the trajectory (which the loss needs), backward (the reverse sweep,
+    reading each step's input from the trajectory: one sub-step per control step), against
+    the plain per-step launch."""
     from workloads import BLUEROV2, CONFIGS, initial_state, actions
     c = CONFIGS["c4"]
     E, T, K = n_envs or c.n_envs, c.n_ctrl, c.extra["ckpt_every"]
@@ -248,7 +250,7 @@ def bench_adjoint(torch, mg, reps=5, n_envs=None):
         ckpt[0], _ = sim.adj_forward(act, K, traj=traj)
 
     t_fwd = timed(fwd)
-    t_bwd = timed(lambda: sim.adj_backward(ckpt[0], act, K, g))
+    t_bwd = timed(lambda: sim.adj_backward(ckpt[0], act, K, g, traj=traj))
 
     def plain():
         sim.set_state(x0)
@@ -259,7 +261,8 @@ def bench_adjoint(torch, mg, reps=5, n_envs=None):
     del traj, g, act, ckpt
     torch.cuda.empty_cache()
     return {"workload": f"{E} BlueROV2 envs, 64 control steps of 10 ms, checkpoint every 8, "
-                        "gradients w.r.t. throttles, 19 hydrodynamic parameters and x0",
+                        "gradients w.r.t. throttles, 19 hydrodynamic parameters and x0; the "
+                        "backward reads each step's input from the forward's trajectory",
             "forward_ms": t_fwd, "backward_ms": t_bwd, "fwd_plus_bwd_ms": t_fwd + t_bwd,
             "cost_vs_forward": (t_fwd + t_bwd) / t_fwd,
             "plain_forward_ms": t_plain, "cost_vs_plain_forward": (t_fwd + t_bwd) / t_plain,

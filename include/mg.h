@@ -327,7 +327,10 @@ mg_status mg_task_counters(mg_sim* sim, int32_t* out);
  *   ckpt     device [ceil(T / ckpt_every)][D][E]  (written)
  *   traj     device [T][D][E] state after each control step, or NULL
  * mg_adj_backward: given dL/d traj, recomputes each segment of ckpt_every
- *   control steps from its checkpoint and sweeps it backwards.  The sub-step
+ *   control steps from its checkpoint and sweeps it backwards.  With one
+ *   sub-step per control step and the forward's trajectory given (traj), the
+ *   input of every step is already there (the row before it; ckpt for the
+ *   first), so nothing is recomputed and no scratch is used.  Otherwise the sub-step
  *   states it linearises about are held in a scratch buffer the sim owns and
  *   keeps until mg_destroy: the whole rollout's (T * substeps * D * E floats)
  *   when that fits in 4 GiB, there is more than one segment and the allocation
@@ -336,6 +339,9 @@ mg_status mg_task_counters(mg_sim* sim, int32_t* out);
  *   just before its sweep.  The gradients are the same, bitwise, either way.
  *   MG_ERR_OOM only when the segment-sized buffer cannot be allocated.
  *   ckpt, actions  as written / read by mg_adj_forward with the same T, ckpt_every
+ *   traj      device [T][D][E] the trajectory that forward wrote, unchanged, or
+ *             NULL (ignored when substeps > 1); the gradients are the same,
+ *             bitwise, with or without it
  *   dL_dtraj  device [T][D][E]
  *   dL_dact   device [T][N_max][E]  (written; rows >= a class's n_thr are 0,
  *             and so is the derivative of a clamped throttle)
@@ -343,9 +349,10 @@ mg_status mg_task_counters(mg_sim* sim, int32_t* out);
  *   dL_dx0    device [D][E] or NULL (written) */
 mg_status mg_adj_forward(mg_sim* sim, const float* actions, int32_t T, int32_t ckpt_every,
                          float* ckpt, float* traj);
-mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, int32_t T,
-                          int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
-                          float* dL_dtheta, float* dL_dx0);
+mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* traj,
+                          const float* actions, int32_t T, int32_t ckpt_every,
+                          const float* dL_dtraj, float* dL_dact, float* dL_dtheta,
+                          float* dL_dx0);
 
 /* mg_adj_backward for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving or training loops, harnesses that forbid
@@ -363,9 +370,10 @@ mg_status mg_adj_backward(mg_sim* sim, const float* ckpt, const float* actions, 
  * sim or stream, race and must be ordered by the caller.  MG_ERR_DEVICE if the
  * scratch was not set up (mg_create looks it up once per device). */
 #define MG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
-mg_status mg_adj_backward_noalloc(mg_sim* sim, const float* ckpt, const float* actions,
-                                  int32_t T, int32_t ckpt_every, const float* dL_dtraj,
-                                  float* dL_dact, float* dL_dtheta, float* dL_dx0);
+mg_status mg_adj_backward_noalloc(mg_sim* sim, const float* ckpt, const float* traj,
+                                  const float* actions, int32_t T, int32_t ckpt_every,
+                                  const float* dL_dtraj, float* dL_dact, float* dL_dtheta,
+                                  float* dL_dx0);
 
 /* ---- serving loop -------------------------------------------------------------------
  * Serves step and rollout requests of uneven env counts from many client

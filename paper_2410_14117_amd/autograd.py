@@ -22,18 +22,20 @@ class FossenRollout(torch.autograd.Function):
         traj = torch.empty((T, sim.state_dim, sim.n_envs), dtype=torch.float32,
                            device=actions.device)
         ckpt, _ = sim.adj_forward(actions, ckpt_every, traj=traj)
-        ctx.save_for_backward(ckpt, actions, params)
+        ctx.save_for_backward(ckpt, actions, params, traj)
         ctx.sim = sim
         ctx.ckpt_every = int(ckpt_every)
         return traj
 
     @staticmethod
     def backward(ctx, g_traj):
-        ckpt, actions, params = ctx.saved_tensors
+        ckpt, actions, params, traj = ctx.saved_tensors
         sim = ctx.sim
         sim.set_params(params)      # the sim may have been used in between
+        # with one sub-step per control step the backward reads each step's input
+        # from the trajectory instead of recomputing it
         gact, gth, gx0 = sim.adj_backward(ckpt, actions, ctx.ckpt_every,
-                                          g_traj.to(torch.float32).contiguous())
+                                          g_traj.to(torch.float32).contiguous(), traj=traj)
         return gx0, gact, gth, None, None, None
 
 

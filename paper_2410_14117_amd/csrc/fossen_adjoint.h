@@ -380,6 +380,20 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
   constexpr int D = Dims<N, LAG>::D;
   const int K = a.ckpt_every, S = a.substeps;
   const int nseg = (a.T + K - 1) / K;
+  // the input of sub-step s of control step t: from the recomputation buffer,
+  // or (WHOLE with recomputed == 2: one sub-step per control step) from the
+  // caller's trajectory row of the step before, the first checkpoint for t = 0
+  auto load_input = [&](int t, int s, int base, float (&y)[D]) {
+    if (WHOLE && a.recomputed == 2) {
+      const float* p = t == 0 ? a.ckpt + c : a.traj + (int64_t)(t - 1) * a.D * a.E + c;
+#pragma unroll
+      for (int i = 0; i < D; ++i) y[i] = p[i * a.E];
+    } else {
+      const float* sb = a.segbuf + (int64_t)((t - base) * S + s) * D * a.Ep + j;
+#pragma unroll
+      for (int i = 0; i < D; ++i) y[i] = sb[i * a.Ep];
+    }
+  };
   float lam[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) lam[i] = 0.0f;
@@ -426,9 +440,7 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
     if constexpr (PREFETCH) {
       float y_n[D], gt_n[D], act_n[N];
       {
-        const float* sb = a.segbuf + (int64_t)((t1 - 1 - base) * S + S - 1) * D * a.Ep + j;
-#pragma unroll
-        for (int i = 0; i < D; ++i) y_n[i] = sb[i * a.Ep];
+        load_input(t1 - 1, S - 1, base, y_n);
         const float* gt = a.gtraj + (int64_t)(t1 - 1) * a.D * a.E + c;
 #pragma unroll
         for (int i = 0; i < D; ++i) gt_n[i] = gt[i * a.E];
@@ -460,12 +472,10 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
           float y[D];
 #pragma unroll
           for (int i = 0; i < D; ++i) y[i] = y_n[i];
-          if (s > 0 || t > t0) {
-            const int row = s > 0 ? (t - base) * S + s - 1 : (t - 1 - base) * S + S - 1;
-            const float* sb = a.segbuf + (int64_t)row * D * a.Ep + j;
-#pragma unroll
-            for (int i = 0; i < D; ++i) y_n[i] = sb[i * a.Ep];
-          }
+          if (s > 0)
+            load_input(t, s - 1, base, y_n);
+          else if (t > t0)
+            load_input(t - 1, S - 1, base, y_n);
           rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
         }
         throttle_vjp<N>(cc, act, fcb, gcb, ab);
@@ -487,9 +497,7 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
         for (int k = 0; k < 6; ++k) gcb[k] = 0.0f;
         for (int s = S - 1; s >= 0; --s) {
           float y[D];
-          const float* sb = a.segbuf + (int64_t)((t - base) * S + s) * D * a.Ep + j;
-#pragma unroll
-          for (int i = 0; i < D; ++i) y[i] = sb[i * a.Ep];
+          load_input(t, s, base, y);
           rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
         }
         throttle_vjp<N>(cc, act, fcb, gcb, ab);

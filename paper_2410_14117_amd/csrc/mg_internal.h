@@ -164,7 +164,8 @@ struct AdjArgs {
   int32_t n_max, D, T, substeps, ckpt_every;
   float dt;
   float* ckpt;                 // caller [ceil(T/K)][D][E]
-  float* traj;                 // caller [T][D][E] or NULL (forward)
+  float* traj;                 // caller [T][D][E] or NULL: written by the forward; read by
+                               // the backward when recomputed == 2
   const float* gtraj;          // caller [T][D][E] dL/d traj (backward)
   float* gact;                 // caller [T][n_max][E]
   float* gtheta;               // caller [19][E]
@@ -173,7 +174,8 @@ struct AdjArgs {
                                // or [T * S][Dc][Ep] when recomputed
   float zb;                    // class z_b (for dL/dB through h_z)
   int32_t n_cu;                // compute units (picks the backward kernel's occupancy)
-  int32_t recomputed;          // segbuf already holds every sub-step input of the rollout
+  int32_t recomputed;          // 1: segbuf already holds every sub-step input of the rollout;
+                               // 2: one sub-step per control step, inputs read from traj
 };
 
 // ---- serving loop (kernels_serve.hip) -------------------------------------

@@ -397,23 +397,26 @@ AdjArgs adj_args(mg_sim* s, const float* actions, int32_t T, int32_t K) {
 
 // The backward's launches: per class, the whole rollout's recomputation into
 // buf (whole) and the reverse sweep, or the sweep that recomputes each segment
-// into buf itself.  Allocates nothing.
-mg_status adj_backward_launch(mg_sim* s, const float* ckpt, const float* actions, int32_t T,
-                              int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
-                              float* dL_dtheta, float* dL_dx0, float* buf, bool whole) {
+// into buf itself; with traj (one sub-step per control step) only the sweep,
+// reading its inputs from traj.  Allocates nothing.
+mg_status adj_backward_launch(mg_sim* s, const float* ckpt, const float* traj,
+                              const float* actions, int32_t T, int32_t ckpt_every,
+                              const float* dL_dtraj, float* dL_dact, float* dL_dtheta,
+                              float* dL_dx0, float* buf, bool whole) {
   AdjArgs a = adj_args(s, actions, T, ckpt_every);
   a.ckpt = const_cast<float*>(ckpt);
+  a.traj = const_cast<float*>(traj);
   a.gtraj = dL_dtraj;
   a.gact = dL_dact;
   a.gtheta = dL_dtheta;
   a.gx0 = dL_dx0;
   a.segbuf = buf;
-  a.recomputed = whole ? 1 : 0;
+  a.recomputed = traj ? 2 : (whole ? 1 : 0);
   for (int k = 0; k < s->n_classes; ++k) {
     a.seg_start = s->seg_start[k];
     a.seg_len = s->seg_len[k];
     a.zb = (float)s->nominal[k].zb;
-    if (whole) MG_HIP(s, launch_adj_recompute(s->cc[k], a, s->stream));
+    if (whole && !traj) MG_HIP(s, launch_adj_recompute(s->cc[k], a, s->stream));
     MG_HIP(s, launch_adjoint(true, s->cc[k], a, s->stream));
   }
   return MG_OK;
@@ -935,14 +938,19 @@ mg_status mg_adj_forward(mg_sim* s, const float* actions, int32_t T, int32_t ckp
   return MG_OK;
 }
 
-mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* actions, int32_t T,
-                          int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
+mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* traj, const float* actions,
+                          int32_t T, int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
                           float* dL_dtheta, float* dL_dx0) {
   mg_status st = adj_common(s, actions, T, ckpt_every, ckpt);
   if (st) return st;
   if (!dL_dtraj || !dL_dact || !dL_dtheta)
     return fail(s, MG_ERR_INVALID, "dL_dtraj, dL_dact and dL_dtheta must not be NULL");
   DeviceGuard g(s->device);
+  // with one sub-step per control step, the forward's trajectory holds every
+  // sub-step input: nothing to recompute, no scratch
+  if (traj && s->substeps == 1)
+    return adj_backward_launch(s, ckpt, traj, actions, T, ckpt_every, dL_dtraj, dL_dact,
+                               dL_dtheta, dL_dx0, nullptr, true);
   // When the rollout's sub-step inputs fit in 4 GiB, every segment is
   // recomputed at once into a whole-rollout buffer and the backward only
   // sweeps: a sparse launch then waits for one segment's recomputation
@@ -982,17 +990,23 @@ mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* actions, in
     }
     s->segbuf_cap = seg_floats;
   }
-  return adj_backward_launch(s, ckpt, actions, T, ckpt_every, dL_dtraj, dL_dact, dL_dtheta,
-                             dL_dx0, s->segbuf, whole);
+  return adj_backward_launch(s, ckpt, nullptr, actions, T, ckpt_every, dL_dtraj, dL_dact,
+                             dL_dtheta, dL_dx0, s->segbuf, whole);
 }
 
-mg_status mg_adj_backward_noalloc(mg_sim* s, const float* ckpt, const float* actions, int32_t T,
-                                  int32_t ckpt_every, const float* dL_dtraj, float* dL_dact,
-                                  float* dL_dtheta, float* dL_dx0) {
+mg_status mg_adj_backward_noalloc(mg_sim* s, const float* ckpt, const float* traj,
+                                  const float* actions, int32_t T, int32_t ckpt_every,
+                                  const float* dL_dtraj, float* dL_dact, float* dL_dtheta,
+                                  float* dL_dx0) {
   mg_status st = adj_common(s, actions, T, ckpt_every, ckpt);
   if (st) return st;
   if (!dL_dtraj || !dL_dact || !dL_dtheta)
     return fail(s, MG_ERR_INVALID, "dL_dtraj, dL_dact and dL_dtheta must not be NULL");
+  if (traj && s->substeps == 1) {
+    DeviceGuard g(s->device);
+    return adj_backward_launch(s, ckpt, traj, actions, T, ckpt_every, dL_dtraj, dL_dact,
+                               dL_dtheta, dL_dx0, nullptr, true);
+  }
   // the same choice as mg_adj_backward, bounded by the static scratch instead
   // of by what can be allocated
   const size_t cap = MG_NOALLOC_SCRATCH_BYTES / sizeof(float);
@@ -1009,8 +1023,8 @@ mg_status mg_adj_backward_noalloc(mg_sim* s, const float* ckpt, const float* act
   DeviceGuard g(s->device);
   float* buf = g_noalloc_ptr[s->device];   // set by mg_create on this device
   if (!buf) return fail(s, MG_ERR_DEVICE, "static adjoint scratch not set up on this device");
-  return adj_backward_launch(s, ckpt, actions, T, ckpt_every, dL_dtraj, dL_dact, dL_dtheta,
-                             dL_dx0, buf, whole);
+  return adj_backward_launch(s, ckpt, nullptr, actions, T, ckpt_every, dL_dtraj, dL_dact,
+                             dL_dtheta, dL_dx0, buf, whole);
 }
 
 mg_status mg_synchronize(mg_sim* s) {

@@ -146,10 +146,10 @@ _SIGS = {
     "mg_task_step": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mg_task_counters": (ctypes.c_int32, [_vp, _vp]),
     "mg_adj_forward": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
-    "mg_adj_backward": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
-                                         _vp, _vp]),
-    "mg_adj_backward_noalloc": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
-                                                 _vp, _vp, _vp, _vp]),
+    "mg_adj_backward": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                         _vp, _vp, _vp, _vp]),
+    "mg_adj_backward_noalloc": (ctypes.c_int32, [_vp, _vp, _vp, _vp, ctypes.c_int32,
+                                                 ctypes.c_int32, _vp, _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -460,10 +460,12 @@ class Sim:
         return ckpt, traj
 
     def adj_backward(self, ckpt, actions, ckpt_every, dL_dtraj, want_x0=True, out=None,
-                     noalloc=False):
+                     noalloc=False, traj=None):
         """Returns (dL/d actions [T][N_max][E], dL/d theta [19][E], dL/d x0 [D][E] or None).
         out: optional (dL_dact, dL_dtheta, dL_dx0 or None) tensors to write into;
-        noalloc: call mg_adj_backward_noalloc (static scratch, no device allocation)."""
+        noalloc: call mg_adj_backward_noalloc (static scratch, no device allocation);
+        traj: the trajectory adj_forward wrote (with one sub-step per control step the
+        backward then reads its inputs from it instead of recomputing them)."""
         import torch
         T, E, D, N = int(actions.shape[0]), self.n_envs, self.state_dim, self.action_dim
         K = int(ckpt_every)
@@ -481,9 +483,10 @@ class Sim:
         ck = _ptr(ckpt, torch.float32, (nseg, D, E), "ckpt")
         a = _ptr(actions, torch.float32, (T, N, E), "actions")
         g = _ptr(dL_dtraj, torch.float32, (T, D, E), "dL_dtraj")
+        tr = _ptr(traj, torch.float32, (T, D, E), "traj")
         self._bind_stream()
         fn = lib().mg_adj_backward_noalloc if noalloc else lib().mg_adj_backward
-        self._check(fn(self._h, ck, a, T, K, g, ga, gt, gx))
+        self._check(fn(self._h, ck, tr, a, T, K, g, ga, gt, gx))
         return gact, gth, gx0
 
 

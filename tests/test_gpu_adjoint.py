@@ -340,3 +340,36 @@ def test_single_segment_one_wave_backward(mgmod, oracle, lag):
         assert _rel(g_act[:, :, e], r_act[:, :, k]) <= TOL_GRAD
         assert _rel(g_th[:, e], r_th[:, k]) <= TOL_GRAD
         assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD
+
+
+@pytest.mark.parametrize("E,lag", [(3000, False), (3000, True), (70000, False)])
+def test_backward_reads_the_trajectory(mgmod, E, lag):
+    """With one sub-step per control step, the backward given the forward's trajectory reads
+    each step's input from it (the row before; the first checkpoint for step 0) instead of
+    recomputing it.  Its gradients equal, bitwise, those of the recomputing backward --
+    whole-rollout (checkpoints every 4) and segment-at-a-time (one segment of 16) -- and of
+    the allocation-free entry point given the trajectory; 3000 envs (one-wave sweep, with
+    and without thruster lag) and 70 000 (two-wave sweep)."""
+    v = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05) if lag else BLUEROV2
+    T = 16
+    sim = mgmod.Sim(v, E, 0.01, 1)
+    D, N = sim.state_dim, sim.action_dim
+    x0 = dev(initial_state(E, D, 501))
+    a = dev(actions(T, N, E, 502) * np.float32(1.1))
+    g = torch.empty((T, D, E), device="cuda").normal_(
+        0.0, 1.0, generator=torch.Generator(device="cuda").manual_seed(503))
+    traj = torch.empty((T, D, E), device="cuda")
+    res = {}
+    for K in (4, 16):
+        sim.reset(state=x0, param_mult=dev(param_multipliers(E, 0.2, 504)))
+        ckpt, _ = sim.adj_forward(a, K, traj=traj)
+        say(f"backward from traj: E={E} lag={lag} K={K}")
+        res[f"recompute{K}"] = sim.adj_backward(ckpt, a, K, g)
+        res[f"traj{K}"] = sim.adj_backward(ckpt, a, K, g, traj=traj)
+        res[f"noalloc{K}"] = sim.adj_backward(ckpt, a, K, g, traj=traj, noalloc=True)
+    torch.cuda.synchronize()
+    sim.close()
+    ref = res["recompute4"]
+    for key, got in res.items():
+        for r, o in zip(ref, got):
+            assert torch.equal(r, o), key

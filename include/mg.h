@@ -340,7 +340,7 @@ mg_status mg_task_counters(mg_sim* sim, int32_t* out);
  *   MG_ERR_OOM only when the segment-sized buffer cannot be allocated.
  *   ckpt, actions  as written / read by mg_adj_forward with the same T, ckpt_every
  *   traj      device [T][D][E] the trajectory that forward wrote, unchanged, or
- *             NULL (ignored when substeps > 1); the gradients are the same,
+ *             NULL (used as above, else ignored); the gradients are the same,
  *             bitwise, with or without it
  *   dL_dtraj  device [T][D][E]
  *   dL_dact   device [T][N_max][E]  (written; rows >= a class's n_thr are 0,

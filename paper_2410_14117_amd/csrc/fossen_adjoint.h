@@ -371,7 +371,12 @@ __host__ __device__ __forceinline__ void recompute_segment(const AdjArgs& a, con
 // behind the current sub-step's VJP (a launch of one wave per SIMD has no
 // other wave to hide it behind); it costs 2 D + N registers, which the
 // two-wave build cannot spare.
-template <int N, bool LAG, bool WHOLE, bool PREFETCH = false>
+// TRAJ (with WHOLE): one sub-step per control step, each step's input read
+// from the caller's trajectory instead of the recomputation buffer; built with
+// one wave per SIMD only (its two-wave build spilled 360 bytes per lane,
+// against 48 for the buffer-reading sweep, and ran at less than half the
+// one-wave build's speed on 2^20 envs).
+template <int N, bool LAG, bool WHOLE, bool PREFETCH = false, bool TRAJ = false>
 __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const ClassConst& cc,
                                                      const EnvConst& P,
                                                      const StepConstT<float>& sc,
@@ -380,11 +385,14 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
   constexpr int D = Dims<N, LAG>::D;
   const int K = a.ckpt_every, S = a.substeps;
   const int nseg = (a.T + K - 1) / K;
+  static_assert(WHOLE || !TRAJ, "trajectory inputs replace the whole-rollout buffer");
   // the input of sub-step s of control step t: from the recomputation buffer,
-  // or (WHOLE with recomputed == 2: one sub-step per control step) from the
-  // caller's trajectory row of the step before, the first checkpoint for t = 0
+  // or (TRAJ: one sub-step per control step) from the caller's trajectory row
+  // of the step before, the first checkpoint for t = 0
   auto load_input = [&](int t, int s, int base, float (&y)[D]) {
-    if (WHOLE && a.recomputed == 2) {
+    if constexpr (TRAJ) {
+      (void)s;
+      (void)base;
       const float* p = t == 0 ? a.ckpt + c : a.traj + (int64_t)(t - 1) * a.D * a.E + c;
 #pragma unroll
       for (int i = 0; i < D; ++i) y[i] = p[i * a.E];

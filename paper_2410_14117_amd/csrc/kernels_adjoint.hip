@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_fwd(const AdjArg
   for (int i = 0; i < D; ++i) a.state[i * a.Ep + j] = x[i];
 }
 
-template <int N, bool LAG, int WAVES, bool WHOLE>
+template <int N, bool LAG, int WAVES, bool WHOLE, bool TRAJ = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAVES)))
 k_adj_bwd(const AdjArgs a, const ClassConst cc) {
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -89,7 +89,7 @@ k_adj_bwd(const AdjArgs a, const ClassConst cc) {
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
-  adj_bwd_env<N, LAG, WHOLE, WAVES == 1>(a, cc, P, sc, A, j, c);
+  adj_bwd_env<N, LAG, WHOLE, WAVES == 1, TRAJ>(a, cc, P, sc, A, j, c);
 }
 
 // Every segment's recomputation at once (blockIdx.y = segment) into the
@@ -148,7 +148,13 @@ static hipError_t launch_adj_t(bool backward, const ClassConst& cc, const AdjArg
   if (nblk == 0) return hipSuccess;
   // one wave per SIMD over the whole device: n_cu CUs x 4 SIMDs x 64 lanes
   const bool crowded = a.seg_len > (int64_t)a.n_cu * 4 * 64;
-  if (backward && a.recomputed && crowded)
+  // the trajectory-reading sweep runs in its one-wave build also when the
+  // launch is crowded: the two-wave build spills inside the VJP, and the
+  // one-wave build, with no recomputation to wait for, is the faster of the two
+  if (backward && a.recomputed == 2)
+    hipLaunchKernelGGL((k_adj_bwd<N, LAG, 1, true, true>), dim3((unsigned)nblk), dim3(kBlock), 0,
+                       s, a, cc);
+  else if (backward && a.recomputed && crowded)
     hipLaunchKernelGGL((k_adj_bwd<N, LAG, 2, true>), dim3((unsigned)nblk), dim3(kBlock), 0, s, a,
                        cc);
   else if (backward && a.recomputed)

@@ -395,6 +395,12 @@ AdjArgs adj_args(mg_sim* s, const float* actions, int32_t T, int32_t K) {
   return a;
 }
 
+// Whether the backward reads its inputs from the forward's trajectory: the
+// caller passed one, and each control step is a single sub-step.
+bool traj_inputs(const mg_sim* s, const float* traj) {
+  return traj && s->substeps == 1;
+}
+
 // The backward's launches: per class, the whole rollout's recomputation into
 // buf (whole) and the reverse sweep, or the sweep that recomputes each segment
 // into buf itself; with traj (one sub-step per control step) only the sweep,
@@ -947,8 +953,9 @@ mg_status mg_adj_backward(mg_sim* s, const float* ckpt, const float* traj, const
     return fail(s, MG_ERR_INVALID, "dL_dtraj, dL_dact and dL_dtheta must not be NULL");
   DeviceGuard g(s->device);
   // with one sub-step per control step, the forward's trajectory holds every
-  // sub-step input: nothing to recompute, no scratch
-  if (traj && s->substeps == 1)
+  // sub-step input: for launches of at most one wave per SIMD nothing is then
+  // recomputed and no scratch is used
+  if (traj_inputs(s, traj))
     return adj_backward_launch(s, ckpt, traj, actions, T, ckpt_every, dL_dtraj, dL_dact,
                                dL_dtheta, dL_dx0, nullptr, true);
   // When the rollout's sub-step inputs fit in 4 GiB, every segment is
@@ -1002,7 +1009,7 @@ mg_status mg_adj_backward_noalloc(mg_sim* s, const float* ckpt, const float* tra
   if (st) return st;
   if (!dL_dtraj || !dL_dact || !dL_dtheta)
     return fail(s, MG_ERR_INVALID, "dL_dtraj, dL_dact and dL_dtheta must not be NULL");
-  if (traj && s->substeps == 1) {
+  if (traj_inputs(s, traj)) {
     DeviceGuard g(s->device);
     return adj_backward_launch(s, ckpt, traj, actions, T, ckpt_every, dL_dtraj, dL_dact,
                                dL_dtheta, dL_dx0, nullptr, true);

@@ -272,9 +272,10 @@ def test_other_instantiations(mgmod, oracle, n_thr, lag):
 @pytest.mark.slow
 def test_full_size_adjoint_sampled(mgmod, oracle):
     """The benchmark's large adjoint configuration: 2^20 BlueROV2 envs (nominal, linear map,
-    no lag), 64 control steps of 10 ms, checkpoints every 8 -- the whole-rollout recompute
-    and the two-wave sweep.  Gradients of 17 envs spread over the range (and the last) match
-    the oracle's dual-number gradients."""
+    no lag), 64 control steps of 10 ms, checkpoints every 8, run as the benchmark runs it:
+    through the autograd wrapper, whose backward reads each step's input from the forward's
+    trajectory (the one-wave sweep over 4096 waves).  Gradients of 17 envs spread over the
+    range (and the last) match the oracle's dual-number gradients."""
     from paper_2410_14117_amd.autograd import rollout
     E, T, K, S, dt = 1 << 20, 64, 8, 1, 0.01
     v = BLUEROV2
@@ -348,8 +349,9 @@ def test_backward_reads_the_trajectory(mgmod, E, lag):
     each step's input from it (the row before; the first checkpoint for step 0) instead of
     recomputing it.  Its gradients equal, bitwise, those of the recomputing backward --
     whole-rollout (checkpoints every 4) and segment-at-a-time (one segment of 16) -- and of
-    the allocation-free entry point given the trajectory; 3000 envs (one-wave sweep, with
-    and without thruster lag) and 70 000 (two-wave sweep)."""
+    the allocation-free entry point given the trajectory; 3000 envs (with and without
+    thruster lag) and 70 000, more than one wave per SIMD, where the recomputing backward
+    takes its two-wave sweep and the trajectory-reading one stays in its one-wave build."""
     v = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05) if lag else BLUEROV2
     T = 16
     sim = mgmod.Sim(v, E, 0.01, 1)

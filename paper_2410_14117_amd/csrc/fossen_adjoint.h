@@ -27,13 +27,52 @@ __host__ __device__ __forceinline__ void theta_bar_zero(ThetaBar<T>& t) {
   t.wmb = t.hz = T(0);
 }
 
+// The same adjoints held in LDS, [20][kBlock] floats (slot k of a lane at
+// col + k kBlock), for the two-wave trajectory-reading sweep, which has 256
+// registers and would otherwise spill inside the sub-step VJP: each
+// += / -= is a load, the same operation and a store, so the sums are those of
+// ThetaBar, bitwise.  theta_bar_fence, a compiler-only memory barrier placed
+// between the stage VJPs, keeps the compiler from holding the slots in
+// registers across them (which would bring the register pressure back); for
+// ThetaBar (registers) it is a no-op.
+struct LdsAcc {
+  float* p;
+  __device__ __forceinline__ void operator+=(float v) const { *p = *p + v; }
+  __device__ __forceinline__ void operator-=(float v) const { *p = *p - v; }
+};
+struct LdsAccRow {
+  float* p;
+  __device__ __forceinline__ LdsAcc operator[](int i) const { return {p + i * kBlock}; }
+};
+struct ThetaBarLds {
+  LdsAccRow ma, dl, dq;
+  LdsAcc wmb, hz;
+};
+// slot k of a lane's column: ma 0-5, dl 6-11, dq 12-17, wmb 18, hz 19
+__device__ __forceinline__ ThetaBarLds theta_bar_lds(float* col) {
+#pragma unroll
+  for (int k = 0; k < 20; ++k) col[k * kBlock] = 0.0f;
+  return {{col}, {col + 6 * kBlock}, {col + 12 * kBlock}, {col + 18 * kBlock},
+          {col + 19 * kBlock}};
+}
+template <class T>
+__host__ __device__ __forceinline__ void theta_bar_fence(ThetaBar<T>&) {}
+__device__ __forceinline__ void theta_bar_fence(ThetaBarLds&) { asm volatile("" ::: "memory"); }
+template <class T>
+__host__ __device__ __forceinline__ T theta_bar_get(const ThetaBar<T>& t, int k) {
+  return k < 6 ? t.ma[k] : k < 12 ? t.dl[k - 6] : k < 18 ? t.dq[k - 12] : k == 18 ? t.wmb : t.hz;
+}
+__device__ __forceinline__ float theta_bar_get(const ThetaBarLds& t, int k) {
+  return *(volatile float*)(t.ma.p + k * kBlock);
+}
+
 // dL/d(x, tau, theta) of xd = rhs_core(x, tau) given xdb = dL/dxd.
 // Accumulates into xb (13 rows; the position rows receive nothing) and thb;
 // writes taub.
-template <class T>
+template <class T, class TB>
 __host__ __device__ __forceinline__ void rhs_core_vjp(const T* x, const EnvConstT<T>& P,
                                                       const T (&tau)[6], const T* xdb, T* xb,
-                                                      T (&taub)[6], ThetaBar<T>& thb) {
+                                                      T (&taub)[6], TB& thb) {
   const T qw = x[3], qx = x[4], qy = x[5], qz = x[6];
   const T u = x[7], v = x[8], w = x[9], p = x[10], q = x[11], r = x[12];
   // forward intermediates
@@ -68,8 +107,8 @@ __host__ __device__ __forceinline__ void rhs_core_vjp(const T* x, const EnvConst
   rb[4] = fma_t(P.Iqq, gq, P.Iuq * gu);
   rb[1] = fma_t(P.Ivp, gp, P.Ivv * gv);
   rb[3] = fma_t(P.Ipp, gp, P.Ivp * gv);
-  rb[2] = P.Iww * gw;
-  rb[5] = P.Irr * gr;
+  rb[2] = mul_nc(P.Iww, gw);
+  rb[5] = mul_nc(P.Irr, gr);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     thb.ma[i] -= rb[i] * nud[i];
@@ -82,25 +121,25 @@ __host__ __device__ __forceinline__ void rhs_core_vjp(const T* x, const EnvConst
   T eb[6];
   // r0 = tau0 + r av - q aw + wmb k0 - e0 u
   nub[5] += av * rb[0]; avb += r * rb[0]; nub[4] -= aw * rb[0]; awb -= q * rb[0];
-  k0b += P.wmb * rb[0]; thb.wmb += k0 * rb[0]; eb[0] = -u * rb[0]; nub[0] -= e[0] * rb[0];
+  k0b += P.wmb * rb[0]; thb.wmb += k0 * rb[0]; eb[0] = mul_nc(-u, rb[0]); nub[0] -= e[0] * rb[0];
   // r1 = tau1 + p aw - r au + wmb k1 - e1 v
   nub[3] += aw * rb[1]; awb += p * rb[1]; nub[5] -= au * rb[1]; aub -= r * rb[1];
-  k1b += P.wmb * rb[1]; thb.wmb += k1 * rb[1]; eb[1] = -v * rb[1]; nub[1] -= e[1] * rb[1];
+  k1b += P.wmb * rb[1]; thb.wmb += k1 * rb[1]; eb[1] = mul_nc(-v, rb[1]); nub[1] -= e[1] * rb[1];
   // r2 = tau2 + q au - p av + wmb k2 - e2 w
   nub[4] += au * rb[2]; aub += q * rb[2]; nub[3] -= av * rb[2]; avb -= p * rb[2];
-  k2b += P.wmb * rb[2]; thb.wmb += k2 * rb[2]; eb[2] = -w * rb[2]; nub[2] -= e[2] * rb[2];
+  k2b += P.wmb * rb[2]; thb.wmb += k2 * rb[2]; eb[2] = mul_nc(-w, rb[2]); nub[2] -= e[2] * rb[2];
   // r3 = tau3 - v aw + w av - q br + r bq - hz k1 - e3 p
   nub[1] -= aw * rb[3]; awb -= v * rb[3]; nub[2] += av * rb[3]; avb += w * rb[3];
   nub[4] -= br * rb[3]; brb -= q * rb[3]; nub[5] += bq * rb[3]; bqb += r * rb[3];
-  k1b -= P.hz * rb[3]; thb.hz -= k1 * rb[3]; eb[3] = -p * rb[3]; nub[3] -= e[3] * rb[3];
+  k1b -= P.hz * rb[3]; thb.hz -= k1 * rb[3]; eb[3] = mul_nc(-p, rb[3]); nub[3] -= e[3] * rb[3];
   // r4 = tau4 - w au + u aw - r bp + p br + hz k0 - e4 q
   nub[2] -= au * rb[4]; aub -= w * rb[4]; nub[0] += aw * rb[4]; awb += u * rb[4];
   nub[5] -= bp * rb[4]; bpb -= r * rb[4]; nub[3] += br * rb[4]; brb += p * rb[4];
-  k0b += P.hz * rb[4]; thb.hz += k0 * rb[4]; eb[4] = -q * rb[4]; nub[4] -= e[4] * rb[4];
+  k0b += P.hz * rb[4]; thb.hz += k0 * rb[4]; eb[4] = mul_nc(-q, rb[4]); nub[4] -= e[4] * rb[4];
   // r5 = tau5 - u av + v au - p bq + q bp - e5 r
   nub[0] -= av * rb[5]; avb -= u * rb[5]; nub[1] += au * rb[5]; aub += v * rb[5];
   nub[3] -= bq * rb[5]; bqb -= p * rb[5]; nub[4] += bp * rb[5]; bpb += q * rb[5];
-  eb[5] = -r * rb[5]; nub[5] -= e[5] * rb[5];
+  eb[5] = mul_nc(-r, rb[5]); nub[5] -= e[5] * rb[5];
   // e_i = d_L,i + d_Q,i |nu_i|   (d|x|/dx taken as +1 at 0)
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -157,12 +196,12 @@ __host__ __device__ __forceinline__ void rhs_core_vjp(const T* x, const EnvConst
 // Reverse of rk4_substep: y is the sub-step input (D rows), lam holds dL/d(output)
 // on entry and dL/dy on exit; dL/d f_cmd and dL/d (B f_cmd) accumulate into fcb and
 // gcb, parameter adjoints into thb.
-template <int N, bool LAG, class T>
+template <int N, bool LAG, class T, class TB>
 __host__ __device__ __forceinline__ void rk4_substep_vjp(const T* y, const EnvConstT<T>& P,
                                                          const ClassConst& cc,
                                                          const T (&fcmd)[N], const T (&gcmd)[6],
                                                          T dt, T* lam, T (&fcb)[N], T (&gcb)[6],
-                                                         ThetaBar<T>& thb) {
+                                                         TB& thb) {
   const T h2 = T(0.5) * dt, h6 = dt * (T(1) / T(6));
   auto fac = [](int i, T f) { return (i >= 3 && i < 7) ? T(0.5) * f : f; };
   T df[N], dg[6], tau1[6], tau2[6], tau3[6], tau4[6];
@@ -171,7 +210,7 @@ __host__ __device__ __forceinline__ void rk4_substep_vjp(const T* y, const EnvCo
     for (int i = 0; i < N; ++i) df[i] = y[13 + i] - fcmd[i];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      T s = T(cc.B[k][0]) * df[0];
+      T s = mul_nc(T(cc.B[k][0]), df[0]);
 #pragma unroll
       for (int i = 1; i < N; ++i) s = fma_t(T(cc.B[k][i]), df[i], s);
       dg[k] = s;
@@ -222,16 +261,17 @@ __host__ __device__ __forceinline__ void rk4_substep_vjp(const T* y, const EnvCo
 #pragma unroll
   for (int i = 0; i < 13; ++i) zb[i] = lam[i];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) zb[3 + i] = (lam[3 + i] - qo[i] * dot) * inv;
+  for (int i = 0; i < 4; ++i) zb[3 + i] = mul_nc(lam[3 + i] - qo[i] * dot, inv);
 
   // combination z' = y + fac(h6) (k1 + 2 k2 + 2 k3 + k4), then the stages in reverse
   T yb[13], kb[13], Xb[13], tb1[6], tb2[6], tb3[6], tb4[6];
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
     yb[i] = zb[i];
-    kb[i] = fac(i, h6) * zb[i];
+    kb[i] = mul_nc(fac(i, h6), zb[i]);
     Xb[i] = T(0);
   }
+  theta_bar_fence(thb);
   rhs_core_vjp(X4, P, tau4, kb, Xb, tb4, thb);          // X4 = y + fac(dt) k3
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
@@ -239,6 +279,7 @@ __host__ __device__ __forceinline__ void rk4_substep_vjp(const T* y, const EnvCo
     kb[i] = fma_t(fac(i, dt), Xb[i], T(2) * fac(i, h6) * zb[i]);
     Xb[i] = T(0);
   }
+  theta_bar_fence(thb);
   rhs_core_vjp(X3, P, tau3, kb, Xb, tb3, thb);          // X3 = y + fac(h2) k2
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
@@ -246,6 +287,7 @@ __host__ __device__ __forceinline__ void rk4_substep_vjp(const T* y, const EnvCo
     kb[i] = fma_t(fac(i, h2), Xb[i], T(2) * fac(i, h6) * zb[i]);
     Xb[i] = T(0);
   }
+  theta_bar_fence(thb);
   rhs_core_vjp(X2, P, tau2, kb, Xb, tb2, thb);          // X2 = y + fac(h2) k1
 #pragma unroll
   for (int i = 0; i < 13; ++i) {
@@ -253,6 +295,7 @@ __host__ __device__ __forceinline__ void rk4_substep_vjp(const T* y, const EnvCo
     kb[i] = fma_t(fac(i, h2), Xb[i], fac(i, h6) * zb[i]);
     Xb[i] = T(0);
   }
+  theta_bar_fence(thb);
   rhs_core_vjp(y, P, tau1, kb, Xb, tb1, thb);           // X1 = y
 #pragma unroll
   for (int i = 0; i < 13; ++i) lam[i] = yb[i] + Xb[i];
@@ -372,16 +415,16 @@ __host__ __device__ __forceinline__ void recompute_segment(const AdjArgs& a, con
 // other wave to hide it behind); it costs 2 D + N registers, which the
 // two-wave build cannot spare.
 // TRAJ (with WHOLE): one sub-step per control step, each step's input read
-// from the caller's trajectory instead of the recomputation buffer; built with
-// one wave per SIMD only (its two-wave build spilled 360 bytes per lane,
-// against 48 for the buffer-reading sweep, and ran at less than half the
-// one-wave build's speed on 2^20 envs).
-template <int N, bool LAG, bool WHOLE, bool PREFETCH = false, bool TRAJ = false>
+// from the caller's trajectory instead of the recomputation buffer.
+// TB: ThetaBar<float> (registers) or ThetaBarLds (LDS), zeroed by the caller;
+// the parameter adjoints accumulate into it and are written out at the end.
+template <int N, bool LAG, bool WHOLE, bool PREFETCH = false, bool TRAJ = false,
+          class TB = ThetaBar<float>>
 __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const ClassConst& cc,
                                                      const EnvConst& P,
                                                      const StepConstT<float>& sc,
                                                      const HalfInvT<float>& A, int64_t j,
-                                                     int64_t c) {
+                                                     int64_t c, TB thb) {
   constexpr int D = Dims<N, LAG>::D;
   const int K = a.ckpt_every, S = a.substeps;
   const int nseg = (a.T + K - 1) / K;
@@ -405,8 +448,6 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
   float lam[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) lam[i] = 0.0f;
-  ThetaBar<float> thb;
-  theta_bar_zero(thb);
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int t0 = seg * K, t1 = min(a.T, t0 + K);
     const int base = WHOLE ? 0 : t0;   // segbuf row of control step t: (t - base) * S
@@ -503,10 +544,16 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
         for (int i = 0; i < N; ++i) fcb[i] = 0.0f;
 #pragma unroll
         for (int k = 0; k < 6; ++k) gcb[k] = 0.0f;
-        for (int s = S - 1; s >= 0; --s) {
+        if constexpr (TRAJ) {   // one sub-step per control step
           float y[D];
-          load_input(t, s, base, y);
+          load_input(t, 0, base, y);
           rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
+        } else {
+          for (int s = S - 1; s >= 0; --s) {
+            float y[D];
+            load_input(t, s, base, y);
+            rk4_substep_vjp<N, LAG>(y, P, cc, fcmd, gcmd, a.dt, lam, fcb, gcb, thb);
+          }
         }
         throttle_vjp<N>(cc, act, fcb, gcb, ab);
         float* ga = a.gact + (int64_t)t * a.n_max * a.E + c;
@@ -518,12 +565,8 @@ __host__ __device__ __forceinline__ void adj_bwd_env(const AdjArgs& a, const Cla
   }
   // theta = (M_A(6), D_L(6), D_Q(6), B);  W - B and h_z = W z_g - B z_b carry B
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    a.gtheta[i * a.E + c] = thb.ma[i];
-    a.gtheta[(6 + i) * a.E + c] = thb.dl[i];
-    a.gtheta[(12 + i) * a.E + c] = thb.dq[i];
-  }
-  a.gtheta[18 * a.E + c] = -thb.wmb - a.zb * thb.hz;
+  for (int k = 0; k < 18; ++k) a.gtheta[k * a.E + c] = theta_bar_get(thb, k);
+  a.gtheta[18 * a.E + c] = -theta_bar_get(thb, 18) - a.zb * theta_bar_get(thb, 19);
   if (a.gx0) {
 #pragma unroll
     for (int i = 0; i < D; ++i) a.gx0[i * a.E + c] = lam[i];

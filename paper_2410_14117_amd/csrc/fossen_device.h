@@ -18,6 +18,20 @@ namespace mg {
 // Scalar helpers; the double versions serve host-side checks of the kernel math.
 __host__ __device__ inline float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 __host__ __device__ inline double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
+// A product never fused into an FMA with the sum it feeds.  Where a product
+// has several uses and one of them is a sum, whether the compiler contracts
+// that sum depends on the rest of the kernel, so two kernels built from the
+// same code (the step, the adjoint's forward and recomputation, the one-wave,
+// two-wave and trajectory-reading sweeps) could round it differently.  The
+// products of that kind go through mul_nc, which keeps results bitwise equal
+// across kernels.
+template <class T>
+__host__ __device__ __forceinline__ T mul_nc(T a, T b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
 __host__ __device__ inline float abs_t(float a) { return fabsf(a); }
 __host__ __device__ inline double abs_t(double a) { return fabs(a); }
 // Used only for 1/|q| with |q|^2 close to 1 (never denormal): the hardware
@@ -242,7 +256,7 @@ __host__ __device__ __forceinline__ void command_wrench(const ClassConst& cc, co
                                                         T (&gcmd)[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    T s = T(cc.B[k][0]) * fcmd[0];
+    T s = mul_nc(T(cc.B[k][0]), fcmd[0]);
 #pragma unroll
     for (int i = 1; i < N; ++i) s = fma_t(T(cc.B[k][i]), fcmd[i], s);
     gcmd[k] = s;
@@ -404,7 +418,7 @@ __host__ __device__ __forceinline__ void lag_wrench(const ClassConst& cc, const 
                                                     const T (&fcmd)[N], T (&dg)[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    T s = T(cc.B[k][0]) * (x[13] - fcmd[0]);
+    T s = mul_nc(T(cc.B[k][0]), x[13] - fcmd[0]);
 #pragma unroll
     for (int i = 1; i < N; ++i) s = fma_t(T(cc.B[k][i]), x[13 + i] - fcmd[i], s);
     dg[k] = s;

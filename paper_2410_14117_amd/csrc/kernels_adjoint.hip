@@ -15,10 +15,15 @@ namespace mg {
 
 // The forward is held to three resident waves per SIMD (168 VGPRs; the few
 // values it then spills lie outside the control-step loop).  The backward
-// kernel needs about 320 registers (VGPRs + AGPRs), one wave per SIMD; its
-// WAVES = 2 instantiation is squeezed into 256 and spills about 50 values
-// inside the sub-step VJP to scratch.  That pays only when the launch has more
-// waves than one per SIMD across the chip (launch_adj_t picks it then).
+// kernel needs about 285-385 registers (VGPRs + AGPRs), one wave per SIMD; its
+// WAVES = 2 instantiation has 256, which pays only when the launch has more
+// waves than one per SIMD across the chip (launch_adj_t picks it then).  The
+// two-wave recomputing sweeps keep the parameter adjoints in registers and
+// spill 13-38 values inside the sub-step VJP; the two-wave trajectory-reading
+// sweep keeps them in LDS (ThetaBarLds, 20 KiB per block) and spills nothing,
+// where in registers it spilled 40-90 values.  (LDS accumulators in the
+// recomputing sweeps removed their spills too, but cost more than the spills:
+// 4.0 against 3.6 ms on 2^20 envs.)
 #ifndef MG_ADJ_FWD_WAVES_PER_EU
 #define MG_ADJ_FWD_WAVES_PER_EU 3
 #endif
@@ -89,7 +94,16 @@ k_adj_bwd(const AdjArgs a, const ClassConst cc) {
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
-  adj_bwd_env<N, LAG, WHOLE, WAVES == 1, TRAJ>(a, cc, P, sc, A, j, c);
+  if constexpr (WAVES == 1 || !TRAJ) {
+    ThetaBar<float> thb;
+    theta_bar_zero(thb);
+    adj_bwd_env<N, LAG, WHOLE, WAVES == 1, TRAJ>(a, cc, P, sc, A, j, c, thb);
+  } else {
+    // two waves per SIMD, trajectory inputs: the parameter adjoints live in LDS
+    __shared__ float thb_lds[20 * kBlock];
+    adj_bwd_env<N, LAG, WHOLE, false, TRAJ>(a, cc, P, sc, A, j, c,
+                                            theta_bar_lds(thb_lds + threadIdx.x));
+  }
 }
 
 // Every segment's recomputation at once (blockIdx.y = segment) into the
@@ -148,10 +162,10 @@ static hipError_t launch_adj_t(bool backward, const ClassConst& cc, const AdjArg
   if (nblk == 0) return hipSuccess;
   // one wave per SIMD over the whole device: n_cu CUs x 4 SIMDs x 64 lanes
   const bool crowded = a.seg_len > (int64_t)a.n_cu * 4 * 64;
-  // the trajectory-reading sweep runs in its one-wave build also when the
-  // launch is crowded: the two-wave build spills inside the VJP, and the
-  // one-wave build, with no recomputation to wait for, is the faster of the two
-  if (backward && a.recomputed == 2)
+  if (backward && a.recomputed == 2 && crowded)
+    hipLaunchKernelGGL((k_adj_bwd<N, LAG, 2, true, true>), dim3((unsigned)nblk), dim3(kBlock), 0,
+                       s, a, cc);
+  else if (backward && a.recomputed == 2)
     hipLaunchKernelGGL((k_adj_bwd<N, LAG, 1, true, true>), dim3((unsigned)nblk), dim3(kBlock), 0,
                        s, a, cc);
   else if (backward && a.recomputed && crowded)

@@ -211,10 +211,12 @@ void check(unsigned seed, int E, int T, int K, int S, int map, float dt) {
     a.recomputed = form == 2;
     for (int e = 0; e < E; ++e) {
       const HalfInvT<float> A = half_step_inverse(Ps[e], sc.h2);
+      ThetaBar<float> thb;
+      theta_bar_zero(thb);
       if (form == 0) {
-        adj_bwd_env<N, LAG, false>(a, cc, Ps[e], sc, A, e, e);
+        adj_bwd_env<N, LAG, false>(a, cc, Ps[e], sc, A, e, e, thb);
       } else if (form == 3) {
-        adj_bwd_env<N, LAG, false, true>(a, cc, Ps[e], sc, A, e, e);
+        adj_bwd_env<N, LAG, false, true>(a, cc, Ps[e], sc, A, e, e, thb);
       } else if (form == 1) {
         adj_bwd_env_factored<N, LAG>(a, cc, Ps[e], sc, A, e, e);
       } else {
@@ -224,7 +226,7 @@ void check(unsigned seed, int E, int T, int K, int S, int map, float dt) {
           recompute_segment<N, LAG>(a, cc, Ps[e], A, sc, x, seg * K, std::min(T, seg * K + K), 0,
                                     e, e);
         }
-        adj_bwd_env<N, LAG, true>(a, cc, Ps[e], sc, A, e, e);
+        adj_bwd_env<N, LAG, true>(a, cc, Ps[e], sc, A, e, e, thb);
       }
     }
     return o;

@@ -126,8 +126,9 @@ __device__ __forceinline__ void derive_constants(const double (&prm)[kNumParams]
                                                  double zb, float (&out)[kNumDerived]) {
   const double m = prm[0];
   const double Muu = m + prm[4], Mvv = m + prm[5], Mww = m + prm[6];
-  const double Mpp = prm[1] + m * zg * zg + prm[7];
-  const double Mqq = prm[2] + m * zg * zg + prm[8];
+  const double mzz = mul_nc(mul_nc(m, zg), zg);   // m z_g^2 (two sums use it)
+  const double Mpp = prm[1] + mzz + prm[7];
+  const double Mqq = prm[2] + mzz + prm[8];
   const double Mrr = prm[3] + prm[9];
   const double Muq = m * zg, Mvp = -m * zg;
   const double det_uq = Muu * Mqq - Muq * Muq, det_vp = Mvv * Mpp - Mvp * Mvp;
@@ -144,7 +145,7 @@ __device__ __forceinline__ void derive_constants(const double (&prm)[kNumParams]
     dv[kDL + i] = prm[10 + i];
     dv[kDQ + i] = prm[16 + i];
   }
-  const double W = m * kG0, B = prm[22];
+  const double W = mul_nc(m, kG0), B = prm[22];
   dv[kWmB] = W - B;
   dv[kHz] = W * zg - B * zb;
 #pragma unroll

@@ -24,7 +24,8 @@ __device__ __forceinline__ RigidInv rigid_inverse(const float* params, int64_t E
                                                   double zg) {
   const double m = params[j], ix = params[Ep + j], iy = params[2 * Ep + j],
                iz = params[3 * Ep + j];
-  const double mpp = ix + m * zg * zg, mqq = iy + m * zg * zg, muq = m * zg, mvp = -m * zg;
+  const double mzz = mul_nc(mul_nc(m, zg), zg);
+  const double mpp = ix + mzz, mqq = iy + mzz, muq = m * zg, mvp = -m * zg;
   const double det_uq = m * mqq - muq * muq, det_vp = m * mpp - mvp * mvp;
   RigidInv I;
   I.uu = (float)(mqq / det_uq);

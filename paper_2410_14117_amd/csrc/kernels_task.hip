@@ -32,7 +32,7 @@ __device__ __forceinline__ void reference(const TaskConst& tc, const double (&c)
     return;
   }
   if (tc.task == 3) {
-    const double s2 = sn * sn, inv = 1.0 / (1.0 + s2);
+    const double s2 = mul_nc(sn, sn), inv = 1.0 / (1.0 + s2);
     pr[0] = c[0] + tc.R * cs * inv;
     pr[1] = c[1] + tc.R * sn * cs * inv;
     pr[2] = c[2];

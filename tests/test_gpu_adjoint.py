@@ -343,15 +343,15 @@ def test_single_segment_one_wave_backward(mgmod, oracle, lag):
         assert _rel(g_x0[:, e], r_x0[:, k]) <= TOL_GRAD
 
 
-@pytest.mark.parametrize("E,lag", [(3000, False), (3000, True), (70000, False)])
+@pytest.mark.parametrize("E,lag", [(3000, False), (3000, True), (70000, False), (70000, True)])
 def test_backward_reads_the_trajectory(mgmod, E, lag):
     """With one sub-step per control step, the backward given the forward's trajectory reads
     each step's input from it (the row before; the first checkpoint for step 0) instead of
     recomputing it.  Its gradients equal, bitwise, those of the recomputing backward --
     whole-rollout (checkpoints every 4) and segment-at-a-time (one segment of 16) -- and of
-    the allocation-free entry point given the trajectory; 3000 envs (with and without
-    thruster lag) and 70 000, more than one wave per SIMD, where the recomputing backward
-    takes its two-wave sweep and the trajectory-reading one stays in its one-wave build."""
+    the allocation-free entry point given the trajectory; 3000 envs and 70 000 (more than
+    one wave per SIMD: two-wave sweeps, the trajectory-reading one with its parameter
+    adjoints in LDS), each with and without thruster lag."""
     v = vehicle_variant(BLUEROV2_HEAVY, thr_map=1, thr_tau=0.05) if lag else BLUEROV2
     T = 16
     sim = mgmod.Sim(v, E, 0.01, 1)

@@ -176,6 +176,30 @@ mg_status mg_set_state(mg_sim* sim, const float* state);
 #define MG_FLAG_NOT_SPD 2
 mg_status mg_get_flags(mg_sim* sim, int32_t* out, int32_t out_on_device);
 
+/* Bounds-checked debug build (not a passage of the paper: a checking aid).
+ * The same sources built with -DMG_DEBUG give libmg_debug.so, with the same
+ * entry points and results.  Its kernels check the indices each lane
+ * addresses against the bounds of the buffers (a class segment within the
+ * padded rows, caller columns within [0, n_envs), internal columns, tick-list
+ * entries, page columns within their request's arrays); a failed check sets
+ * its bit in a device word and that lane does nothing further, so it never
+ * accesses memory out of bounds.  Bits: MG_DBG_SEGMENT, MG_DBG_COLUMN,
+ * MG_DBG_INTERNAL, MG_DBG_LIST, MG_DBG_PAGE.
+ * mg_debug_build: 1 in the debug build, 0 in the release build.
+ * mg_debug_word: waits for the sim's stream, then stores the word in *word
+ *   and zeroes it when clear != 0; the release build always stores 0.
+ *   NULL word: MG_ERR_INVALID.
+ * Test hook of the debug build: MG_DEBUG_SHRINK=k in the environment when a
+ * sim is created makes its kernels treat caller columns >= n_envs - k as out
+ * of bounds (those envs are skipped, and MG_DBG_COLUMN is set). */
+#define MG_DBG_SEGMENT 1
+#define MG_DBG_COLUMN 2
+#define MG_DBG_INTERNAL 4
+#define MG_DBG_LIST 8
+#define MG_DBG_PAGE 16
+int32_t mg_debug_build(void);
+mg_status mg_debug_word(mg_sim* sim, uint32_t* word, int32_t clear);
+
 /* Advances every env by n_ctrl control steps in ONE fused launch per class:
  * each control step reads one throttle frame, holds it for `substeps` RK4
  * sub-steps, and the state stays in registers across all n_ctrl * substeps
@@ -511,6 +535,11 @@ mg_status mg_server_wait(mg_server* srv, uint64_t ticket, int64_t timeout_us, do
  * ticket. */
 mg_status mg_server_cancel(mg_server* srv, uint64_t ticket);
 mg_status mg_server_get_stats(const mg_server* srv, mg_server_stats* out);
+
+/* The server's failed-check word of the debug build (mg_debug_word); read it
+ * while no request is in flight.  Release build: 0.  NULL srv or word:
+ * MG_ERR_INVALID. */
+mg_status mg_server_debug_word(mg_server* srv, uint32_t* word, int32_t clear);
 const char* mg_server_last_error(const mg_server* srv);
 /* Stops accepting requests, finishes every request already submitted, joins
  * the scheduler and frees everything; NULL is ignored. */

@@ -17,6 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmg.so")
+DEBUG_LIB = os.path.join(HERE, "libmg_debug.so")   # bounds-checked build (-DMG_DEBUG)
 CLIENTS_LIB = os.path.join(HERE, "libmg_clients.so")
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 
@@ -83,6 +84,15 @@ def build_clients(verbose=True):
         print(f"built {CLIENTS_LIB}")
 
 
+def build_debug(verbose=True):
+    """The bounds-checked build of the same sources (-DMG_DEBUG) as libmg_debug.so: same
+    entry points and results, kernels that check every lane's indices (include/mg.h)."""
+    return build(verbose, out=DEBUG_LIB, build_dir=BUILD + "_debug", defines=("MG_DEBUG",))
+
+
 if __name__ == "__main__":
-    build()
+    if "--debug" in sys.argv[1:]:
+        build_debug()
+    else:
+        build()
     sys.exit(0)

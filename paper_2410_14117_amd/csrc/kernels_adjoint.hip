@@ -38,8 +38,10 @@ __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_fwd(const AdjArg
   constexpr int D = Dims<N, LAG>::D;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;
+  if (!MG_CHECK(a, a.seg_start + a.seg_len <= a.Ep, kDbgSegment)) return;
   const int64_t j = a.seg_start + local;
   const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
+  if (!MG_CHECK(a, c >= 0 && c < a.dbg.cols, kDbgColumn)) return;
   float x[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) x[i] = a.state[i * a.Ep + j];
@@ -89,8 +91,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WAV
 k_adj_bwd(const AdjArgs a, const ClassConst cc) {
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;
+  if (!MG_CHECK(a, a.seg_start + a.seg_len <= a.Ep, kDbgSegment)) return;
   const int64_t j = a.seg_start + local;
   const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
+  if (!MG_CHECK(a, c >= 0 && c < a.dbg.cols, kDbgColumn)) return;
   const EnvConst P = load_env_const(a.derived, a.Ep, j);
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   const HalfInvT<float> A = half_step_inverse(P, sc.h2);
@@ -117,8 +121,10 @@ __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_recompute(const 
   constexpr int D = Dims<N, LAG>::D;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;
+  if (!MG_CHECK(a, a.seg_start + a.seg_len <= a.Ep, kDbgSegment)) return;
   const int64_t j = a.seg_start + local;
   const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
+  if (!MG_CHECK(a, c >= 0 && c < a.dbg.cols, kDbgColumn)) return;
   const int seg = blockIdx.y;
   const int t0 = seg * a.ckpt_every, t1 = min(a.T, t0 + a.ckpt_every);
   const EnvConst P = load_env_const(a.derived, a.Ep, j);

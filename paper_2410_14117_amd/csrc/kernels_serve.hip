@@ -11,14 +11,16 @@ namespace mg {
 __global__ void __launch_bounds__(64) k_serve_join(const ServeInitItem* __restrict__ items,
                                                    ServeTickItem* __restrict__ list,
                                                    const ClassNominal* __restrict__ nominal,
-                                                   int32_t Dmax) {
+                                                   int32_t Dmax, const DebugArgs dbg) {
   const ServeInitItem it = items[blockIdx.x];
   const int lane = threadIdx.x;
-  if (lane == 0) list[it.list_index] = it.item;
+  if (lane == 0 && MG_CHECK_WITH(dbg, it.list_index >= 0 && it.list_index < dbg.list, kDbgList))
+    list[it.list_index] = it.item;
   const int32_t col32 = it.cols_src[lane];
   it.cols[lane] = col32;
   const int64_t col = col32;
   if (col < 0) return;
+  if (!MG_CHECK_WITH(dbg, col < it.ld, kDbgPage)) return;
   const ClassNominal& nom = nominal[it.cls];
   double prm[kNumParams];
 #pragma unroll
@@ -54,6 +56,7 @@ __device__ __forceinline__ void serve_page(const ServeTickItem& it, const ClassC
   constexpr int D = Dims<N, LAG>::D;
   const int64_t col = it.cols[lane];
   if (col < 0) return;
+  if (!MG_CHECK(a, col < (it.actions ? it.ld : it.n), kDbgPage)) return;
   const StepConstT<float> sc = make_step_const(cc, a.dt);
   float x[D];
 #pragma unroll
@@ -107,6 +110,7 @@ __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickArgs a) {
       idx -= a.count[c];
       ++c;
     }
+    if (!MG_CHECK(a, idx < a.list_cap, kDbgList)) continue;
     const ServeTickItem it = a.list[(int64_t)c * a.list_cap + idx];
     if (!it.block) continue;
     const ClassConst& cc = a.cc[c];
@@ -129,10 +133,10 @@ __global__ void __launch_bounds__(kBlock) k_serve_tick(const ServeTickArgs a) {
 // one block of 64 threads per finished page
 __global__ void __launch_bounds__(64) k_serve_leave(const ServeGatherItem* __restrict__ items,
                                                     ServeTickItem* __restrict__ list,
-                                                    int32_t Dmax) {
+                                                    int32_t Dmax, const DebugArgs dbg) {
   const ServeGatherItem it = items[blockIdx.x];
   const int lane = threadIdx.x;
-  if (lane == 0) {
+  if (lane == 0 && MG_CHECK_WITH(dbg, it.list_index >= 0 && it.list_index < dbg.list, kDbgList)) {
     ServeTickItem z;
     z.block = nullptr;
     z.cols = nullptr;
@@ -147,13 +151,16 @@ __global__ void __launch_bounds__(64) k_serve_leave(const ServeGatherItem* __res
   }
   const int64_t col = it.cols[lane];
   if (col < 0) return;
+  if (!MG_CHECK_WITH(dbg, col < it.n, kDbgPage)) return;
   for (int i = 0; i < Dmax; ++i) it.out[i * it.n + col] = it.block[i * kPageEnvs + lane];
 }
 
 hipError_t launch_serve_join(const ServeInitItem* items, int32_t n_items, ServeTickItem* list,
-                             const ClassNominal* nominal, int32_t Dmax, hipStream_t s) {
+                             const ClassNominal* nominal, int32_t Dmax, const DebugArgs& dbg,
+                             hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_serve_join, dim3(n_items), dim3(64), 0, s, items, list, nominal, Dmax);
+  hipLaunchKernelGGL(k_serve_join, dim3(n_items), dim3(64), 0, s, items, list, nominal, Dmax,
+                     dbg);
   return hipGetLastError();
 }
 
@@ -164,9 +171,9 @@ hipError_t launch_serve_tick(const ServeTickArgs& a, int32_t grid, hipStream_t s
 }
 
 hipError_t launch_serve_leave(const ServeGatherItem* items, int32_t n_items, ServeTickItem* list,
-                              int32_t Dmax, hipStream_t s) {
+                              int32_t Dmax, const DebugArgs& dbg, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_serve_leave, dim3(n_items), dim3(64), 0, s, items, list, Dmax);
+  hipLaunchKernelGGL(k_serve_leave, dim3(n_items), dim3(64), 0, s, items, list, Dmax, dbg);
   return hipGetLastError();
 }
 

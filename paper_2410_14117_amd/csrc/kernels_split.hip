@@ -46,8 +46,10 @@ __global__ void __launch_bounds__(kBlock) k_split(const SplitArgs a, const Class
   constexpr int D = Dims<N, LAG>::D;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;
+  if (!MG_CHECK(a, a.seg_start + a.seg_len <= a.Ep, kDbgSegment)) return;
   const int64_t j = a.seg_start + local;
   const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
+  if (!MG_CHECK(a, c >= 0 && c < a.dbg.cols, kDbgColumn)) return;
   float x[D], acc[6], ma[6];
 #pragma unroll
   for (int i = 0; i < D; ++i) x[i] = a.state[i * a.Ep + j];

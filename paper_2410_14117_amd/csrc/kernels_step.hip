@@ -58,14 +58,17 @@ __global__ void __launch_bounds__(kBlock) MG_STEP_ATTR k_step(const StepArgs a, 
   const int n_ctrl = PLAIN ? 1 : a.n_ctrl;
   const int substeps = PLAIN ? 1 : a.substeps;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool active = local < a.seg_len;
+  bool active = local < a.seg_len &&
+                MG_CHECK(a, a.seg_start + a.seg_len <= a.Ep, kDbgSegment);
   const int64_t j = a.seg_start + (active ? local : 0);
   // byte offsets of the lane's env in internal and caller rows (rows of at most
   // 2^30 floats, checked by the launcher): every access below is a wave-uniform
   // row pointer plus this 32-bit offset, which the compiler addresses as an
   // SGPR base plus a VGPR offset, with no per-access 64-bit index arithmetic
   const uint32_t jo = (uint32_t)j * 4u;
-  const int64_t c = active ? (a.perm ? (int64_t)lane_elem(a.perm, jo) : j) : 0;
+  int64_t c = active ? (a.perm ? (int64_t)lane_elem(a.perm, jo) : j) : 0;
+  active = active && MG_CHECK(a, c >= 0 && c < a.dbg.cols, kDbgColumn);
+  c = active ? c : 0;
   const uint32_t co = (uint32_t)c * 4u;
 
   float x[D];
@@ -216,8 +219,10 @@ __global__ void __launch_bounds__(256) k_reset(const ResetArgs a) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= a.n) return;
   const int64_t id = a.ids ? a.ids[k] : k;
-  if (id < 0 || id >= a.E) return;
+  if (id < 0 || id >= a.E) return;   // out-of-range ids are skipped (documented)
+  if (!MG_CHECK(a, id < a.dbg.cols, kDbgColumn)) return;
   const int64_t j = a.iperm ? (int64_t)a.iperm[id] : id;
+  if (!MG_CHECK(a, j >= 0 && j < a.Ep, kDbgInternal)) return;
   const ClassNominal& nom = a.nominal[a.class_of[j]];
   const bool spd = set_env_params(nom, a.param_in ? a.param_in + k : nullptr, a.n,
                                   a.param_absolute != 0, a.params, a.derived, a.Ep, j);

@@ -119,8 +119,10 @@ k_task(const TaskArgs a, const ClassConst cc, const TaskConst tc) {
   constexpr int D = Dims<N, LAG>::D;
   const int64_t local = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (local >= a.seg_len) return;
+  if (!MG_CHECK(a, a.seg_start + a.seg_len <= a.Ep, kDbgSegment)) return;
   const int64_t j = a.seg_start + local;
   const int64_t c = a.perm ? (int64_t)a.perm[j] : j;
+  if (!MG_CHECK(a, c >= 0 && c < a.dbg.cols, kDbgColumn)) return;
   float x[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) x[i] = a.state[i * a.Ep + j];

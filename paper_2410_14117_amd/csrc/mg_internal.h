@@ -66,6 +66,41 @@ struct ClassNominal {
 constexpr uint8_t kFlagNonFinite = 1;
 constexpr uint8_t kFlagNotSPD = 2;
 
+// Debug build (compiled with -DMG_DEBUG, libmg_debug.so): the kernels check
+// the indices their lanes address against the bounds of the buffers, and a
+// failed check sets its bit in the device word `word` and the lane does no
+// work, so a failed check never leads to an access out of bounds.  In the
+// release build dbg_check is `true` and the checks compile to nothing.
+constexpr uint32_t kDbgSegment = 1;  // a class segment reaches past the padded stride Ep
+constexpr uint32_t kDbgColumn = 2;   // a caller column (perm, reset ids) outside [0, cols)
+constexpr uint32_t kDbgInternal = 4; // an internal column (iperm) outside [0, Ep)
+constexpr uint32_t kDbgList = 8;     // a tick-list entry outside the list
+constexpr uint32_t kDbgPage = 16;    // a page column outside its request's arrays
+struct DebugArgs {
+  uint32_t* word;  // device word of failed-check bits (debug build), else NULL
+  int64_t cols;    // bound of caller columns: E (lower under MG_DEBUG_SHRINK, a test hook)
+  int64_t list;    // entries of the serving tick list
+};
+__device__ __forceinline__ bool dbg_check(const DebugArgs& d, bool ok, uint32_t bit) {
+  if (!ok) atomicOr(d.word, bit);
+  return ok;
+}
+// The argument structs carry `dbg` in the debug build only, so that the
+// release build's kernels are the same code as without the checks; MG_CHECK
+// (args, condition, bit) is `true` there and its operands are not evaluated.
+// MG_CHECK_WITH(d, condition, bit) does the same with a DebugArgs d.
+#ifdef MG_DEBUG
+#define MG_DBG_FIELD DebugArgs dbg;
+#define MG_CHECK_WITH(d, ok, bit) ::mg::dbg_check((d), (ok), (bit))
+#define MG_CHECK(args, ok, bit) ::mg::dbg_check((args).dbg, (ok), (bit))
+#define MG_SET_DBG(args, value) ((args).dbg = (value))
+#else
+#define MG_DBG_FIELD
+#define MG_CHECK_WITH(d, ok, bit) true
+#define MG_CHECK(args, ok, bit) true
+#define MG_SET_DBG(args, value) ((void)0)
+#endif
+
 struct StepArgs {
   float* state;                // internal [D][Ep]
   uint8_t* flags;              // internal [Ep] status flags (read, set when an env freezes)
@@ -83,6 +118,7 @@ struct StepArgs {
   int32_t nblk_total, blk_off;
   int32_t n_ctrl, substeps;
   float dt;
+  MG_DBG_FIELD
 };
 
 struct ResetArgs {
@@ -104,6 +140,7 @@ struct ResetArgs {
   int32_t write_state;         // 0: keep the state
   int32_t* task_k;             // internal [Ep] episode counters zeroed with the state, or NULL
   float* split_acc;            // internal [6][Ep] split-scheme accelerations zeroed likewise, or NULL
+  MG_DBG_FIELD
 };
 
 // Gym-style task of Sec. III (wave-uniform, by value): kind, look-ahead
@@ -134,6 +171,7 @@ struct TaskArgs {
   int32_t* done;               // caller [E] or NULL
   const float* reset_state;    // caller [D][E] or NULL (rest at the origin)
   const float* reset_mult;     // caller [23][E] or NULL (parameters kept)
+  MG_DBG_FIELD
 };
 
 // The split scheme of Sec. II (rigid body by semi-implicit Euler, the
@@ -152,6 +190,7 @@ struct SplitArgs {
   float* traj;                 // caller [n_ctrl][D][E] or NULL
   float dt;
   double zg;                   // this class's CG height below the CO
+  MG_DBG_FIELD
 };
 
 struct AdjArgs {
@@ -176,6 +215,7 @@ struct AdjArgs {
   int32_t n_cu;                // compute units (picks the backward kernel's occupancy)
   int32_t recomputed;          // 1: segbuf already holds every sub-step input of the rollout;
                                // 2: one sub-step per control step, inputs read from traj
+  MG_DBG_FIELD
 };
 
 // ---- serving loop (kernels_serve.hip) -------------------------------------
@@ -225,18 +265,20 @@ struct ServeTickArgs {         // one tick over the pages of every class
   int32_t steps;               // most control steps a page advances
   int32_t Dmax, n_max, substeps;
   float dt;
+  MG_DBG_FIELD
 };
 // joins: initialise each admitted page (one 64-lane block per page) and enter
 // it in the tick list
 hipError_t launch_serve_join(const ServeInitItem* items, int32_t n_items, ServeTickItem* list,
-                             const ClassNominal* nominal, int32_t Dmax, hipStream_t s);
+                             const ClassNominal* nominal, int32_t Dmax, const DebugArgs& dbg,
+                             hipStream_t s);
 // one launch advances the pages of all classes (a wave per page, persistent
 // over `grid` blocks)
 hipError_t launch_serve_tick(const ServeTickArgs& a, int32_t grid, hipStream_t s);
 // leaves: copy each finished page's states into its request's staging and
 // empty its tick-list entry
 hipError_t launch_serve_leave(const ServeGatherItem* items, int32_t n_items, ServeTickItem* list,
-                              int32_t Dmax, hipStream_t s);
+                              int32_t Dmax, const DebugArgs& dbg, hipStream_t s);
 
 // launchers (kernels_adjoint.hip)
 hipError_t launch_adjoint(bool backward, const ClassConst& cc, const AdjArgs& a, hipStream_t s);

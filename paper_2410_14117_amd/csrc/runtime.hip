@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -105,6 +106,9 @@ struct mg_sim {
   int32_t* task_k = nullptr;   // [Ep] control steps since each env's episode began
   // split scheme (mg_step_split): each env's acceleration of its last sub-step
   float* split_acc = nullptr;  // [6][Ep]
+  // bounds checks of the debug build: the failed-check word (NULL in the
+  // release build) and the bounds the kernels check against
+  DebugArgs dbg{};
 };
 
 // Class constants the step kernels read from scalar registers.
@@ -262,6 +266,7 @@ mg_status enqueue_steps(mg_sim* s, hipStream_t st, const float* actions, int32_t
   std::memset(&a, 0, sizeof(a));
   a.state = s->state;
   a.flags = s->flags;
+  MG_SET_DBG(a, s->dbg);
   a.derived = s->derived;
   a.Ep = s->Ep;
   a.E = s->E;
@@ -319,6 +324,7 @@ mg_status reset_impl(mg_sim* s, const int64_t* ids, int64_t n, const float* stat
   std::memset(&r, 0, sizeof(r));
   r.state = s->state;
   r.flags = s->flags;
+  MG_SET_DBG(r, s->dbg);
   r.params = s->params;
   r.derived = s->derived;
   r.Ep = s->Ep;
@@ -392,6 +398,7 @@ AdjArgs adj_args(mg_sim* s, const float* actions, int32_t T, int32_t K) {
   a.ckpt_every = K;
   a.dt = (float)s->dt;
   a.n_cu = s->n_cu;
+  MG_SET_DBG(a, s->dbg);
   return a;
 }
 
@@ -448,6 +455,7 @@ mg_status enqueue_task(mg_sim* s, const float* actions, float* obs, float* err, 
   std::memset(&a, 0, sizeof(a));
   a.state = s->state;
   a.flags = s->flags;
+  MG_SET_DBG(a, s->dbg);
   a.params = s->params;
   a.derived = s->derived;
   a.task_f = s->task_f;
@@ -628,6 +636,21 @@ mg_status mg_create(const mg_config* cfg, mg_sim** out) {
     (void)hipGetLastError();
     return bail(MG_ERR_DEVICE, "device initialisation failed in mg_create");
   }
+  // the debug build's failed-check word; MG_DEBUG_SHRINK=k (read here, debug
+  // build only) makes the kernels treat caller columns >= E - k as out of
+  // bounds, so that a test can see the checks fire while every access stays in
+  // bounds (those lanes only skip their work)
+  s->dbg.cols = E;
+  s->dbg.list = 0;
+#ifdef MG_DEBUG
+  if (hipMalloc(&s->dbg.word, sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(s->dbg.word, 0, sizeof(uint32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(MG_ERR_OOM, "debug word allocation failed in mg_create");
+  }
+  if (const char* sh = std::getenv("MG_DEBUG_SHRINK"))
+    s->dbg.cols = std::max<int64_t>(0, E - std::atoll(sh));
+#endif
   for (int k = 1; k < s->n_classes; ++k) {
     hipStream_t hs = nullptr;
     hipEvent_t e1 = nullptr, e2 = nullptr;
@@ -669,7 +692,7 @@ void mg_destroy(mg_sim* s) {
     for (hipEvent_t e : s->ev_join) (void)hipEventDestroy(e);
     void* bufs[] = {s->state, s->params, s->derived, s->perm, s->iperm, s->class_of, s->flags,
                     s->nominal_dev, s->partials, s->staging, s->segbuf, s->task_f, s->task_k,
-                    s->split_acc};
+                    s->split_acc, s->dbg.word};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     (void)hipGetLastError();
@@ -741,6 +764,27 @@ mg_status mg_get_flags(mg_sim* s, int32_t* out, int32_t out_on_device) {
   return MG_OK;
 }
 
+int32_t mg_debug_build(void) {
+#ifdef MG_DEBUG
+  return 1;
+#else
+  return 0;
+#endif
+}
+
+mg_status mg_debug_word(mg_sim* s, uint32_t* word, int32_t clear) {
+  mg_status st = check_usable(s);
+  if (st) return st;
+  if (!word) return fail(s, MG_ERR_INVALID, "word is NULL");
+  *word = 0;
+  if (!s->dbg.word) return MG_OK;
+  DeviceGuard g(s->device);
+  MG_HIP(s, hipStreamSynchronize(s->stream));
+  MG_HIP(s, hipMemcpy(word, s->dbg.word, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (clear) MG_HIP(s, hipMemset(s->dbg.word, 0, sizeof(uint32_t)));
+  return MG_OK;
+}
+
 mg_status mg_step(mg_sim* s, const float* actions, int32_t n_ctrl, const float* targets,
                   float* traj, double* stats) {
   return step_common(s, actions, n_ctrl, targets, traj, stats, false);
@@ -762,6 +806,7 @@ mg_status mg_step_split(mg_sim* s, const float* actions, int32_t n_ctrl, float* 
   SplitArgs a;
   std::memset(&a, 0, sizeof(a));
   a.state = s->state;
+  MG_SET_DBG(a, s->dbg);
   a.params = s->params;
   a.derived = s->derived;
   a.acc = s->split_acc;

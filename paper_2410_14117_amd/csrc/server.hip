@@ -210,6 +210,7 @@ struct mg_server {
   // put while its request runs); entries are reused lowest index first
   ServeTickItem* list_d = nullptr;
   size_t list_cap = 0;
+  uint32_t* dbg_word = nullptr;       // the debug build's failed-check word, else NULL
   std::vector<std::set<int32_t>> free_entries;
   std::vector<int32_t> hw;            // per class: entries in use are below hw
   int32_t max_grid = 1024;            // blocks of the tick launch (4 pages each) at most
@@ -245,6 +246,15 @@ struct mg_server {
 };
 
 namespace {
+
+// bounds of the debug build's checks in the serving kernels (scheduler thread)
+DebugArgs serve_dbg(const mg_server* S) {
+  DebugArgs d;
+  d.word = S->dbg_word;
+  d.cols = INT64_MAX;
+  d.list = (int64_t)S->list_cap * S->n_classes;
+  return d;
+}
 
 bool fail_server(mg_server* S, const std::string& msg) {
   {
@@ -395,7 +405,7 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
       }
     }
     SV_HIP(launch_serve_join(sl.init.dev, (int32_t)n_init, S->list_d, S->nominal_dev, S->D,
-                             S->stream));
+                             serve_dbg(S), S->stream));
     for (Request* r : admitted) S->active.push_back(r);
     admitted.clear();
   }
@@ -422,6 +432,7 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
   }
   ServeTickArgs a;
   std::memset(&a, 0, sizeof(a));
+  MG_SET_DBG(a, serve_dbg(S));
   a.list = S->list_d;
   a.cc = S->cc_dev;
   a.list_cap = (int64_t)S->list_cap;
@@ -506,7 +517,8 @@ bool launch_tick(mg_server* S, mg_server::Slot& sl, std::vector<Request*>& admit
         --S->hw[c];
       }
     }
-    SV_HIP(launch_serve_leave(sl.gather.dev, (int32_t)n_gat, S->list_d, S->D, S->stream));
+    SV_HIP(launch_serve_leave(sl.gather.dev, (int32_t)n_gat, S->list_d, S->D, serve_dbg(S),
+                              S->stream));
     SV_HIP(hipMemcpyAsync(sl.out->h, sl.out->d, n_out * sizeof(float), hipMemcpyDeviceToHost,
                           S->stream));
   }
@@ -784,6 +796,14 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out) {
   // reservation sizes it for every reserved page
   S->list_cap = (size_t)std::max<int64_t>(
       8192, std::min<int64_t>(cap_pages, std::max<int64_t>(0, cfg->reserve_bytes) / page_bytes));
+#ifdef MG_DEBUG
+  if (hipMalloc(&S->dbg_word, sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(S->dbg_word, 0, sizeof(uint32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    mg_server_destroy(S.release());
+    return bad(MG_ERR_OOM, "debug word allocation failed");
+  }
+#endif
   {
     std::vector<ServeTickItem> z(S->list_cap * S->n_classes);
     std::memset(z.data(), 0, z.size() * sizeof(ServeTickItem));
@@ -927,6 +947,21 @@ mg_status mg_server_wait(mg_server* S, uint64_t ticket, int64_t timeout_us, doub
   return S->book.wait(ticket, timeout_us, latency_s);
 }
 
+mg_status mg_server_debug_word(mg_server* S, uint32_t* word, int32_t clear) {
+  if (!S || !word) return MG_ERR_INVALID;
+  *word = 0;
+  if (!S->dbg_word) return MG_OK;
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  if (prev != S->device) (void)hipSetDevice(S->device);
+  const bool ok =
+      hipMemcpy(word, S->dbg_word, sizeof(uint32_t), hipMemcpyDeviceToHost) == hipSuccess &&
+      (!clear || hipMemset(S->dbg_word, 0, sizeof(uint32_t)) == hipSuccess);
+  if (!ok) (void)hipGetLastError();
+  if (prev >= 0 && prev != S->device) (void)hipSetDevice(prev);
+  return ok ? MG_OK : MG_ERR_DEVICE;
+}
+
 mg_status mg_server_get_stats(const mg_server* S, mg_server_stats* out) {
   if (!S || !out) return MG_ERR_INVALID;
   out->completed = S->completed.load();
@@ -970,6 +1005,7 @@ void mg_server_destroy(mg_server* S) {
     delete m;
   }
   if (S->list_d) (void)hipFree(S->list_d);
+  if (S->dbg_word) (void)hipFree(S->dbg_word);
   for (float* b : S->slab_blocks) (void)hipFree(b);
   for (int32_t* c : S->slab_cols) (void)hipFree(c);
   if (S->nominal_dev) (void)hipFree(S->nominal_dev);

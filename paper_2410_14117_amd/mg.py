@@ -11,6 +11,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MG_LIBRARY") or os.path.join(HERE, "libmg.so")
+# the bounds-checked build (python -m paper_2410_14117_amd.build --debug); select it with
+# MG_LIBRARY=<its path> before this module is imported
+DEBUG_LIB_PATH = os.path.join(HERE, "libmg_debug.so")
+# failed-check bits of the debug build (include/mg.h)
+MG_DBG_SEGMENT, MG_DBG_COLUMN, MG_DBG_INTERNAL, MG_DBG_LIST, MG_DBG_PAGE = 1, 2, 4, 8, 16
 
 MG_ABI_VERSION = 4
 MAX_THR = 8
@@ -129,6 +134,10 @@ _SIGS = {
     "mg_get_params": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
     "mg_synchronize": (ctypes.c_int32, [_vp]),
     "mg_get_flags": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32]),
+    "mg_debug_build": (ctypes.c_int32, []),
+    "mg_debug_word": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32]),
+    "mg_server_debug_word": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_uint32),
+                                              ctypes.c_int32]),
     "mg_clock_ns": (ctypes.c_uint64, []),
     "mg_server_create": (ctypes.c_int32, [ctypes.POINTER(MgServerConfig), ctypes.POINTER(_vp)]),
     "mg_server_submit": (ctypes.c_int32, [_vp, ctypes.POINTER(MgRequest),
@@ -439,6 +448,14 @@ class Sim:
         self._check(lib().mg_get_flags(self._h, out.data_ptr(), 1))
         return out
 
+    def debug_word(self, clear=True):
+        """Failed-check bits of the debug build's kernels (MG_DBG_*; always 0 in the release
+        build); waits for the sim's stream."""
+        w = ctypes.c_uint32(0)
+        self._bind_stream()
+        self._check(lib().mg_debug_word(self._h, ctypes.byref(w), 1 if clear else 0))
+        return w.value
+
     # -- adjoint ---------------------------------------------------------------------------
     def adj_forward(self, actions, ckpt_every, ckpt=None, traj=None):
         """Rollout of T = actions.shape[0] control steps from the current state, saving a
@@ -631,6 +648,14 @@ class Server:
 
     def last_error(self):
         return (lib().mg_server_last_error(self._h) or b"").decode()
+
+    def debug_word(self, clear=True):
+        """The server's failed-check bits (debug build; 0 in the release build)."""
+        w = ctypes.c_uint32(0)
+        st = lib().mg_server_debug_word(self._h, ctypes.byref(w), 1 if clear else 0)
+        if st:
+            raise RuntimeError(f"mg_server_debug_word failed: {st}")
+        return w.value
 
     def stats(self):
         s = MgServerStats()

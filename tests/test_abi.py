@@ -25,6 +25,21 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_debug_build_exports_the_same_symbols_and_says_so():
+    """libmg_debug.so (the bounds-checked build of the same sources) exports every symbol
+    include/mg.h declares; mg_debug_build tells the two builds apart."""
+    if not os.path.exists(mg.DEBUG_LIB_PATH):
+        pytest.skip("libmg_debug.so not built (python -m paper_2410_14117_amd.build --debug)")
+    D = ctypes.CDLL(mg.DEBUG_LIB_PATH)
+    missing = [n for n in _declared("mg.h") if not hasattr(D, n)]
+    assert not missing, missing
+    assert D.mg_debug_build() == 1 and mg.lib().mg_debug_build() == 0
+    assert D.mg_abi_version() == mg.MG_ABI_VERSION
+    w = ctypes.c_uint32(7)
+    assert mg.lib().mg_debug_word(None, ctypes.byref(w), 0) == mg.MG_ERR_INVALID
+    assert mg.lib().mg_server_debug_word(None, ctypes.byref(w), 0) == mg.MG_ERR_INVALID
+
+
 def test_client_driver_exports_every_declared_symbol():
     text = open(os.path.join(ROOT, "include", "mg_clients.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)

@@ -108,6 +108,9 @@ typedef struct {
   void* stream;
 } mg_config;
 
+/* Library plumbing (no passage of the paper defines these): the ABI version
+ * this library implements (MG_ABI_VERSION of its build), and a static text
+ * for a status code ("unknown status" for codes it does not know). */
 uint32_t mg_abi_version(void);
 const char* mg_status_str(mg_status s);
 /* Text of the last failure of this sim, or of the last failed mg_create when
@@ -131,7 +134,7 @@ void mg_destroy(mg_sim* sim);
  * the same GPU (Sec. III); NULL sim: MG_ERR_INVALID. */
 mg_status mg_set_stream(mg_sim* sim, void* stream);
 int32_t mg_state_dim(const mg_sim* sim);      /* D, or -1 for NULL */
-int32_t mg_action_dim(const mg_sim* sim);     /* N_max = largest n_thr, or -1 */
+int32_t mg_action_dim(const mg_sim* sim);     /* N_max = largest n_thr (Sec. II thrusters), or -1 */
 int64_t mg_num_envs(const mg_sim* sim);       /* E, or -1 */
 
 /* Domain randomisation and reset (Sec. II: physical-parameter randomisation).
@@ -509,6 +512,8 @@ typedef struct {
   int64_t max_issue_ns, grow_events, held_joins, deferred_retires;
 } mg_server_stats;
 
+/* The server's clock (std::chrono::steady_clock, ns): the time base of arrival stamps
+ * and latencies (plumbing, no passage of the paper). */
 uint64_t mg_clock_ns(void);
 /* Starts the scheduler thread; page memory is taken in slabs as needed up to the cap. */
 mg_status mg_server_create(const mg_server_config* cfg, mg_server** out);

@@ -520,7 +520,8 @@ mg_status mg_server_create(const mg_server_config* cfg, mg_server** out);
 /* Thread-safe.  MG_ERR_INVALID for a malformed request or one whose pages exceed
  * the whole cap (counted as rejected); MG_ERR_BUSY if the queue is full. */
 mg_status mg_server_submit(mg_server* srv, const mg_request* req, uint64_t* ticket);
-/* Waits up to timeout_us (< 0: forever) for a ticket; MG_OK once its result is in
+/* Waits up to timeout_us (< 0: forever; 0: a poll that returns at once) for a
+ * ticket; MG_OK once its result is in
  * out (the ticket is then consumed and *latency_s, if not NULL, receives
  * arrival-to-completion seconds), MG_ERR_BUSY on timeout, MG_ERR_INVALID for an
  * unknown or already consumed ticket (also for a second thread waiting on a

@@ -65,11 +65,14 @@ __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_fwd(const AdjArg
 #pragma unroll
       for (int i = 0; i < N; ++i) nxt[i] = af[i * a.E];
     }
+    // checkpoints and trajectory rows are written once and read back only by
+    // the backward, after the whole forward: non-temporal stores keep them
+    // from displacing the throttle frames in the caches (2^20 envs: 2-4 %)
     if (t % a.ckpt_every == 0) {
       float* ck = a.ckpt + (int64_t)(t / a.ckpt_every) * a.D * a.E + c;
 #pragma unroll
-      for (int i = 0; i < D; ++i) ck[i * a.E] = x[i];
-      for (int i = D; i < a.D; ++i) ck[i * a.E] = 0.0f;
+      for (int i = 0; i < D; ++i) __builtin_nontemporal_store(x[i], ck + i * a.E);
+      for (int i = D; i < a.D; ++i) __builtin_nontemporal_store(0.0f, ck + i * a.E);
     }
     float fcmd[N], gcmd[6];
     thrust_command<N>(cc, act, fcmd);
@@ -78,8 +81,8 @@ __global__ void __launch_bounds__(kBlock) MG_ADJ_FWD_ATTR k_adj_fwd(const AdjArg
     if (a.traj) {
       float* tf = a.traj + (int64_t)t * a.D * a.E + c;
 #pragma unroll
-      for (int i = 0; i < D; ++i) tf[i * a.E] = x[i];
-      for (int i = D; i < a.D; ++i) tf[i * a.E] = 0.0f;
+      for (int i = 0; i < D; ++i) __builtin_nontemporal_store(x[i], tf + i * a.E);
+      for (int i = D; i < a.D; ++i) __builtin_nontemporal_store(0.0f, tf + i * a.E);
     }
   }
 #pragma unroll

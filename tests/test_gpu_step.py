@@ -485,6 +485,58 @@ def test_few_thruster_classes(mgmod, oracle, n_thr):
     assert rel_err(tr, ref["traj"]) <= 1e-4
 
 
+@pytest.mark.parametrize("empty_first", [True, False])
+def test_declared_class_without_envs(mgmod, empty_first):
+    """A sim that declares a class no env belongs to (a lagged Heavy: its segment is empty,
+    so every launcher skips it, while the I/O widths follow it: D = 21, N_max = 8) steps
+    fused, per sub-step and from a graph, runs the split scheme and the adjoint exactly as
+    a sim of the one populated class (BlueROV2, D = 13): bitwise, with the extra state and
+    action rows zero.  The empty class comes first or second."""
+    E, S, dt, T, K = 500, 4, 0.005, 6, 2
+    heavy = LAGGED["heavy"]
+    classes = [heavy, BLUEROV2] if empty_first else [BLUEROV2, heavy]
+    cls = np.full(E, 1 if empty_first else 0, np.int32)
+    x0 = initial_state(E, 13, 71)
+    mult = param_multipliers(E, 0.2, 72)
+    act6 = actions(T, 6, E, 73)
+    g13 = np.random.default_rng(74).standard_normal((T, 13, E)).astype(np.float32)
+    x0w, act8, g21 = (np.zeros((21, E), np.float32), np.zeros((T, 8, E), np.float32),
+                      np.zeros((T, 21, E), np.float32))
+    x0w[:13], act8[:, :6], g21[:, :13] = x0, act6, g13
+    say("declared class without envs", "first" if empty_first else "second")
+    res = {}
+    for name, sim, xs, ac, g in (("one", mgmod.Sim(BLUEROV2, E, dt, S), x0, act6, g13),
+                                 ("two", mgmod.Sim(classes, E, dt, S, env_class=cls), x0w,
+                                  act8, g21)):
+        D = sim.state_dim
+        a = dev(ac)
+        sim.reset(state=dev(xs), param_mult=dev(mult))
+        traj = torch.empty((3, D, E), device="cuda")
+        stats = torch.empty((3, 4), dtype=torch.float64, device="cuda")
+        sim.step(a[:3], traj=traj, stats=stats)
+        sim.step(a[3:4], plain=True)
+        sim.rollout(a[4:6])
+        r = {"traj": host(traj), "stats": host(stats), "state": host(sim.get_state())}
+        sim.reset(state=dev(xs), param_mult=dev(mult))
+        sim.step_split(a[:2])
+        r["split"] = host(sim.get_state())
+        sim.reset(state=dev(xs), param_mult=dev(mult))
+        tr = torch.empty((T, D, E), device="cuda")
+        ck, _ = sim.adj_forward(a, K, traj=tr)
+        ga, gt, gx = sim.adj_backward(ck, a, K, dev(g))
+        r.update(adj_traj=host(tr), gact=host(ga), gtheta=host(gt), gx0=host(gx))
+        sim.close()
+        res[name] = r
+    one, two = res["one"], res["two"]
+    np.testing.assert_array_equal(two["stats"], one["stats"])
+    np.testing.assert_array_equal(two["gtheta"], one["gtheta"])
+    for k in ("traj", "state", "split", "adj_traj", "gx0"):
+        np.testing.assert_array_equal(two[k][..., :13, :], one[k], err_msg=k)
+        assert (two[k][..., 13:, :] == 0).all(), k
+    np.testing.assert_array_equal(two["gact"][:, :6], one["gact"])
+    assert (two["gact"][:, 6:] == 0).all()
+
+
 def test_invalid_calls_raise_and_leave_the_sim_usable(mgmod):
     """Zero control steps, a task step before a task is configured and a split step of zero
     control steps are rejected (MG_ERR_INVALID) without touching the state."""

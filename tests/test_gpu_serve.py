@@ -72,6 +72,38 @@ def _serve(srv, pools, reqs):
 R = (1234, 1000, 20)     # the request that is checked alone and in the mix
 
 
+def test_malformed_requests_refused_and_a_one_env_step_served(mgmod, pools):
+    """Malformed requests (no envs, no steps, a row stride below the env count, a class
+    the server does not have, no throttles and no seed) are refused with MG_ERR_INVALID
+    before anything is queued (none counts as rejected for the cap); then the smallest
+    request, one env for one control step, is served and equals mg_step bitwise."""
+    from paper_2410_14117_amd.mg import MG_ERR_INVALID
+    srv = mgmod.Server(CLASSES, DT, S)
+    say("serve malformed requests")
+    bad = [dict(_req(pools, 0, 5, 1), n_envs=0), dict(_req(pools, 0, 5, 1), n_steps=0),
+           dict(_req(pools, 0, 5, 1), ld=4), dict(_req(pools, 0, 5, 1), actions_ptr=0),
+           dict(_req(pools, 0, 5, 1), env_class=np.array([0, 1, 2, 0, 1]))]
+    for kw in bad:
+        n = kw["n_envs"]
+        out = np.zeros((D, max(n, 1)), np.float32)
+        if n == 0:
+            kw = dict(kw, env_class=None)
+            out = np.zeros((D, 0), np.float32)
+        assert srv.submit(out=out, **kw)[0] == MG_ERR_INVALID, kw
+    st = srv.stats()
+    assert st["queued"] == 0 and st["completed"] == 0 and st["rejected"] == 0
+    off = 777
+    out = np.zeros((D, 1), np.float32)
+    stt, t = srv.submit(out=out, **_req(pools, off, 1, 1))
+    assert stt == 0 and srv.wait(t, 60_000_000)[0] == 0
+    srv.close()
+    sim = mgmod.Sim(CLASSES, 1, DT, S, env_class=pools["cls"][off:off + 1])
+    sim.reset(state=dev(pools["x0"][:, off:off + 1]), param_mult=dev(pools["mult"][:, off:off + 1]))
+    sim.step(dev(pools["act"][:1, :, off:off + 1]))
+    np.testing.assert_array_equal(host(sim.get_state()), out)
+    sim.close()
+
+
 def test_alone_equals_mix_equals_step_and_oracle(mgmod, pools, oracle):
     say("serve alone")
     srv = mgmod.Server(CLASSES, DT, S)

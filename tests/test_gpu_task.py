@@ -187,8 +187,9 @@ def test_reset_zeroes_episode_counters(mgmod):
 
 
 def test_nonfinite_env_terminates_and_restarts(mgmod):
-    """A non-positive-definite mass matrix makes an env non-finite: done 1, and it restarts
-    from its reset state with the reset multipliers (finite again at the next step)."""
+    """A non-positive-definite mass matrix makes an env non-finite: its reset flags it
+    MG_FLAG_NOT_SPD, the task step reports done 1 and restarts it from its reset state with
+    the reset multipliers (finite again at the next step), which clears the flag."""
     E = 64
     cls, x0, act, mult, center, phase, yaw, rs, _ = _inputs(E, 2, 81)
     mult = mult.copy()
@@ -198,9 +199,12 @@ def test_nonfinite_env_terminates_and_restarts(mgmod):
     sim.reset(state=dev(x0), param_mult=dev(mult))
     sim.task_configure(_task("station", episode_steps=100), dev(center), dev(phase), dev(yaw))
     act_d, rs_d = dev(act), dev(rs)
+    fl = host(sim.get_flags())
+    assert fl[5] == 2 and np.count_nonzero(fl) == 1
     ones = torch.ones((23, E), dtype=torch.float32, device="cuda")
     _, _, d0 = sim.task_step(act_d[0], reset_state=rs_d, reset_mult=ones)
     d0 = host(d0).copy()
+    assert np.count_nonzero(host(sim.get_flags())) == 0
     o1, _, d1 = sim.task_step(act_d[1], reset_state=rs_d, reset_mult=ones)
     d1, o1 = host(d1), host(o1)
     sim.close()
